@@ -1,0 +1,38 @@
+/*
+ * dg_oracle.h -- interface of the plain FP64 CPU oracle (test infrastructure
+ * only; see dg_oracle.c).  Host arrays only.  State layout:
+ * w[cell][field][mode], cell = i + n0 (j + n1 k), mode = l_x + p (l_y + p l_z),
+ * fields (rho, rho v_x, rho v_y[, rho v_z], e[, alpha]).
+ */
+#ifndef DG_ORACLE_H
+#define DG_ORACLE_H
+
+typedef struct {
+    int dim;           /* 2 or 3 */
+    int n[3];          /* cells per axis */
+    int bc[3];         /* 0 periodic, 1 outflow (mirrored ghost) */
+    double h;          /* cubic cell size */
+    int order;         /* p = n + 1 modes and Gauss points per axis */
+    double gamma, nu, kappa;
+    int av_on;
+    double av_scale, f_v, f_tau, f_w, s_onset, alpha_max;
+    double cfl;
+    const double *forcing; /* [cell][3][p^d] coefficients of s, or NULL */
+} or_params;
+
+void or_legendre(int lmax, double x, double *Pt, double *dPt);
+void or_gauss(int n, double *x, double *w);
+void or_euler_flux(int d, double gamma, const double *u, int a, double *f);
+void or_hllc(int d, double gamma, const double *uL, const double *uR, int a, double *F);
+double or_recovery_fraction(int order);
+void or_recover_face(const or_params *pr, const double *wL, const double *wR, int a, double *ut, double *gt);
+double or_sensor(int p, int d, const double *wrho);
+double or_sensor_rate(int p, int d, const double *wrho, const double *wdrho);
+void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *wdot, double *R_out);
+double or_max_dt(const or_params *pr, const double *w, double *cmax_out, double *vmax_out);
+int or_rk_stages(int order);
+void or_step(const or_params *pr, double *w, double dt, double *R_state);
+void or_totals(const or_params *pr, const double *w, double *out);
+int or_num_threads(void);
+
+#endif
