@@ -1,0 +1,165 @@
+/*
+ * dg.h -- C ABI of the MI355X discontinuous-Galerkin hydrodynamics library.
+ *
+ * The library evaluates the right-hand side of the DG weight equations of
+ * Cernetic, Springel, Guillet & Pakmor (arXiv 2208.11131) for the compressible
+ * Euler / Navier-Stokes equations on a uniform Cartesian mesh of cubic cells
+ * with a per-cell tensor-product Legendre basis, and advances them with SSP
+ * Runge-Kutta steps under a CFL time step.
+ *
+ * Conventions shared by every call:
+ *   - Order p (the `order` argument) = n + 1 = modes = Gauss points per axis,
+ *     1 <= p <= 8 (Sec. 2.3, 2.4).  Modes per field: p^dim (tensor set Q_n).
+ *   - State layout (device, float64, C-contiguous): w[cell][field][mode],
+ *     cell = i + n0 (j + n1 k), mode = l_x + p (l_y + p l_z); fields
+ *     (rho, rho v_x, rho v_y[, rho v_z], e[, alpha]): dim + 2 conserved fields
+ *     plus the artificial-viscosity field alpha when AV is enabled (Sec. 4.1).
+ *     w_0 of each field is the cell mean (orthonormal basis, Sec. 2.2).
+ *   - Every pointer argument named w, wdot, s_coeffs or R is a DEVICE pointer
+ *     owned by the caller (e.g. a torch tensor), 8-byte aligned; `stream` is a
+ *     hipStream_t passed as void* (NULL = default stream).  Calls enqueue work
+ *     on that stream and return without waiting, except where stated.
+ *   - Errors are reported by the return code; nothing aborts or throws across
+ *     the ABI.  DG_EINVAL leaves every buffer untouched.
+ *   - One context per stream at a time: calls on one context are not
+ *     thread-safe and must not overlap on different streams.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;
+
+typedef enum {
+    DG_OK = 0,
+    DG_EINVAL = -1,         /* invalid argument (no side effect) */
+    DG_ENOMEM = -2,         /* device allocation failed */
+    DG_EDEVICE = -3,        /* HIP runtime / launch error */
+    DG_ENONPHYSICAL = -4,   /* a cell-mean density or pressure <= 0 (Sec. 4.2) */
+    DG_ENONFINITE = -5,     /* a non-finite weight was produced */
+    DG_EUNSUPPORTED = -6    /* valid request this build does not implement */
+} dg_status;
+
+typedef enum { DG_BC_PERIODIC = 0, DG_BC_OUTFLOW = 1 } dg_bc;
+
+/* Mesh: dim in {2,3}; n[a] cells on [lo[a], hi[a]] along axis a (entries of
+ * unused axes ignored).  Cells must be cubic: (hi-lo)/n equal on every axis
+ * to 1e-12 relative (Sec. 2.1).  DG_BC_OUTFLOW uses a mirrored ghost cell,
+ * w_ghost(l_a) = (-1)^{l_a} w(l_a), on both ends of that axis. */
+typedef struct {
+    int dim;
+    int n[3];
+    double lo[3], hi[3];
+    int bc[3];
+} dg_mesh;
+
+/* Artificial viscosity (Sec. 4.1, eqs. timedependentviscosity and
+ * viscosu_flux_with_factor): dalpha/dt = f_v max(0, -div v)
+ *   + f_w max(0, dlnS/dt) [S > s_onset/p^2] - alpha p c_s / (f_tau h),
+ * eps = scale * clamp(alpha, 0, alpha_max) * c_s * h / p.
+ * Paper defaults: scale 1, f_v 2.5, f_tau 0.5, f_w 0.2, s_onset 1e-4,
+ * alpha_max 1 (dg_av_defaults fills them). */
+typedef struct {
+    int enabled;
+    double scale, f_v, f_tau, f_w, s_onset, alpha_max;
+} dg_av_params;
+
+/* Precision of the bulk arithmetic: FP64 everywhere, or FP32 for the
+ * contractions, point fluxes, Riemann and recovery (state, RK combination,
+ * time step and totals stay FP64). */
+typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_BULK = 1 } dg_precision;
+
+/* Options (NULL = defaults): precision FP64; basis 0 = tensor set Q_n (the
+ * only basis of this build); cfl = f_CFL of eq. timestep (default 0.5);
+ * cells_per_block / faces_per_block: launch tiles, 0 = built-in table. */
+typedef struct {
+    int precision;
+    int basis;
+    double cfl;
+    int cells_per_block;
+    int faces_per_block;
+} dg_options;
+
+void dg_av_defaults(dg_av_params *av);
+void dg_options_defaults(dg_options *opt);
+
+/* Create a context: validates the mesh and physics, builds the basis,
+ * quadrature and recovery tables (Sec. 2.3, 2.4, 3.2) and allocates the
+ * library-owned device buffers (RK registers, face-flux buffer, sensor
+ * scalars, time-step scalars).  gamma > 1; nu (kinematic viscosity) and
+ * kappa (thermal diffusivity chi of Sec. 3.3) >= 0; av NULL or disabled =
+ * no AV field.  Uses the current HIP device.  *out = NULL on error. */
+dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, double kappa,
+                  const dg_av_params *av, const dg_options *opt, dg_ctx **out);
+
+/* Free the context and its device buffers (NULL is ignored). */
+void dg_free(dg_ctx *ctx);
+
+/* Number of doubles of a state array: cells * fields * order^dim. */
+size_t dg_state_len(const dg_ctx *ctx);
+/* Number of fields per cell (dim + 2, + 1 with AV). */
+int dg_num_fields(const dg_ctx *ctx);
+
+/* wdot = dw/dt of the weight equations (Sec. 2.2 eq. weight_evolution,
+ * discretised as Sec. 2.4 eq. time_stepping_final_analytical_equation, with
+ * the viscous and AV fluxes of Sec. 3 and 4).  w and wdot must not overlap.
+ * The AV wiggle source uses the context's stored dlnS/dt of the previous
+ * step (0 after dg_init). */
+dg_status dg_rhs(dg_ctx *ctx, const double *w, double *wdot, void *stream);
+
+/* One SSP Runge-Kutta step of size dt > 0, in place (Sec. 2.5): forward
+ * Euler for p = 1, SSPRK(2,2) for p = 2, SSPRK(3,3) for p = 3, the 5-stage
+ * 4th-order SSPRK(5,4) for p >= 4.  Stage 1 also stores dlnS/dt of w for the
+ * next step's wiggle source.  Sets the context's device error flag when a
+ * stage produces a non-positive cell-mean density/pressure or a non-finite
+ * weight (read it with dg_check). */
+dg_status dg_step(dg_ctx *ctx, double *w, double dt, void *stream);
+
+/* As dg_step, with dt = f_CFL h / (2 p (c_max + v_max)) computed on the
+ * device from w (eq. timestep) and never copied to the host; if dt_dev is
+ * not NULL the step size (double) is also stored there (device pointer). */
+dg_status dg_step_cfl(dg_ctx *ctx, double *w, double *dt_dev, void *stream);
+
+/* Time step of eq. timestep: maxima of the sound speed and of |v| over all
+ * volume Gauss points of w.  Synchronises `stream`; *dt_out is a host
+ * pointer.  cmax_out / vmax_out (host, may be NULL) receive the maxima. */
+dg_status dg_max_dt(dg_ctx *ctx, const double *w, double *dt_out, double *cmax_out, double *vmax_out,
+                    void *stream);
+
+/* Conserved totals sum_K |K| w_0 per conserved field (dim + 2 values, host
+ * pointer `out`), deterministic compensated FP64 sums.  Synchronises. */
+dg_status dg_conserved_totals(dg_ctx *ctx, const double *w, double *out, void *stream);
+
+/* Body-force acceleration field s (Sec. 7 driving): device array
+ * [cell][dim][order^dim] of DG coefficients, read by every later RHS as the
+ * momentum source rho s and energy source rho s.v, projected on the basis.
+ * The library keeps the pointer (caller keeps the memory alive); NULL
+ * removes the forcing. */
+dg_status dg_set_forcing(dg_ctx *ctx, const double *s_coeffs);
+
+/* Per-cell d ln S / dt used by the wiggle source (Sec. 4.1): copy from /
+ * to a caller device array of ncells doubles (checkpointing, tests). */
+dg_status dg_set_sensor_rate(dg_ctx *ctx, const double *R, void *stream);
+dg_status dg_get_sensor_rate(dg_ctx *ctx, double *R, void *stream);
+
+/* Synchronise `stream`, read and clear the device error flag: DG_OK,
+ * DG_ENONPHYSICAL or DG_ENONFINITE. */
+dg_status dg_check(dg_ctx *ctx, void *stream);
+
+/* Launch tiles in use (cells per volume block, threads per volume block,
+ * faces per face block, threads per face block). */
+dg_status dg_get_tiles(const dg_ctx *ctx, int *vol_cells, int *vol_threads, int *face_cells,
+                       int *face_threads);
+
+const char *dg_status_str(dg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

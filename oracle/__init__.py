@@ -62,6 +62,7 @@ def _load():
             "or_sensor": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, _D]),
             "or_sensor_rate": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, _D, _D]),
             "or_rhs": (None, [P, _D, _D, _D, _D]),
+            "or_rhs_cells": (None, [P, _D, _D, ctypes.c_long, ctypes.POINTER(ctypes.c_long), _D]),
             "or_max_dt": (ctypes.c_double, [P, _D, _D, _D]),
             "or_rk_stages": (ctypes.c_int, [ctypes.c_int]),
             "or_step": (None, [P, _D, ctypes.c_double, _D]),
@@ -129,6 +130,17 @@ class Problem:
         Rp = None if R_prev is None else np.ascontiguousarray(R_prev, dtype=np.float64)
         lib.or_rhs(ctypes.byref(self.p), _ptr(w), _ptr(Rp), _ptr(out), _ptr(R_out))
         return (out, R_out) if want_R else out
+
+    def rhs_cells(self, w, cells, R_prev=None):
+        """RHS of the listed cells only (whole state w as input)."""
+        lib = _load()
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros((len(cells), self.nfields, self.nmodes))
+        Rp = None if R_prev is None else np.ascontiguousarray(R_prev, dtype=np.float64)
+        lib.or_rhs_cells(ctypes.byref(self.p), _ptr(w), _ptr(Rp), len(cells),
+                         cells.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _ptr(out))
+        return out
 
     def step(self, w, dt, R_state=None):
         """One SSP-RK step; returns (w_new, R_new)."""

@@ -42,6 +42,7 @@
  *     state; AV diffuses the conserved fields, not the AV field itself;
  *   - sensor threshold s_onset / p^2; wiggle source uses d ln S / dt from
  *     stage 1 of the previous step and the sensor S of the current stage state;
+ *     d ln S / dt is set to 0 where S <= s_onset / p^2 (rounding-level S);
  *   - epsilon uses clamp(alpha, 0, alpha_max); the stored alpha is unclamped;
  *   - RK: p=1 forward Euler, p=2 SSPRK(2,2), p=3 SSPRK(3,3), p>=4 SSPRK(5,4)
  *     of Spiteri & Ruuth (2002) in Shu-Osher form;
@@ -560,22 +561,19 @@ double or_sensor_rate(int p, int d, const double *wrho, const double *wdrho)
  * extended by Sec. 3 and 4).  R_prev: per-cell d ln S/dt of the previous step
  * (wiggle source, NULL = 0).  If R_out != NULL, R_out[c] receives the new
  * d ln S/dt of this state (Sec. 4.1). */
-void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *wdot, double *R_out)
+static void rhs_cell(const or_params *pr, const double *w, const double *R_prev, long c, double *out,
+                     double *R_out_c)
 {
     const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = d + 2;
     const int M = ipow(p, d), NP = M;
-    const long NC = n_cells(pr);
     const double h = pr->h;
     const double pref = pow(2.0, 1 - d) / h;     /* 2^(1-d)/h */
     const double spref = pow(2.0, -d);           /* 2^(-d): source projection */
     const int grad = need_grad(pr);
     double xg[OR_MAXP + 2], wg[OR_MAXP + 2];
     or_gauss(p, xg, wg);
-
-#pragma omp parallel for schedule(dynamic, 4)
-    for (long c = 0; c < NC; ++c) {
+    {
         const double *wc = w + c * (long)F * M;
-        double *out = wdot + c * (long)F * M;
         for (int i = 0; i < F * M; ++i) out[i] = 0.0;
         double S_cur = or_sensor(p, d, wc);
         double wig = 0.0;
@@ -700,8 +698,30 @@ void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *
         }
         free(nb);
         free(Fh);
-        if (R_out && pr->av_on) R_out[c] = or_sensor_rate(p, d, wc, out);
+        /* d ln S/dt is kept only where S itself exceeds the onset threshold:
+         * below it S is at rounding level and its log-rate is noise (the
+         * wiggle trigger of Sec. 4.1 acts only above S_onset). */
+        if (R_out_c && pr->av_on)
+            *R_out_c = (S_cur > pr->s_onset / ((double)p * p)) ? or_sensor_rate(p, d, wc, out) : 0.0;
     }
+}
+
+void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *wdot, double *R_out)
+{
+    const int M = ipow(pr->order, pr->dim), F = n_fields(pr);
+    const long NC = n_cells(pr);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long c = 0; c < NC; ++c) rhs_cell(pr, w, R_prev, c, wdot + c * (long)F * M, R_out ? R_out + c : NULL);
+}
+
+/* RHS of the listed cells only (out[i] = dw/dt of cell cells[i]); w is the
+ * whole state.  Used to check sampled cells of large states. */
+void or_rhs_cells(const or_params *pr, const double *w, const double *R_prev, long ncells_sel, const long *cells,
+                  double *out)
+{
+    const int M = ipow(pr->order, pr->dim), F = n_fields(pr);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < ncells_sel; ++i) rhs_cell(pr, w, R_prev, cells[i], out + i * (long)F * M, NULL);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -29,6 +29,8 @@ void or_recover_face(const or_params *pr, const double *wL, const double *wR, in
 double or_sensor(int p, int d, const double *wrho);
 double or_sensor_rate(int p, int d, const double *wrho, const double *wdrho);
 void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *wdot, double *R_out);
+void or_rhs_cells(const or_params *pr, const double *w, const double *R_prev, long ncells_sel, const long *cells,
+                  double *out);
 double or_max_dt(const or_params *pr, const double *w, double *cmax_out, double *vmax_out);
 int or_rk_stages(int order);
 void or_step(const or_params *pr, double *w, double dt, double *R_state);

@@ -1,0 +1,295 @@
+"""MI355X discontinuous-Galerkin hydrodynamics (arXiv 2208.11131 hot path).
+
+Thin ctypes binding of ``libdgmi.so`` (the HIP kernels and host runtime behind
+the C ABI of ``include/dg.h``).  The functions below carry the same names as
+the C entry points and only marshal arguments: torch tensors supply device
+memory and streams; every step of the computation runs in the library's
+kernels.  There is no fallback: if the library is not built, or no GPU is
+visible, the calls raise.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgmi.so")
+
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_ENONPHYSICAL, DG_ENONFINITE, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+DG_BC_PERIODIC, DG_BC_OUTFLOW = 0, 1
+DG_PREC_FP64, DG_PREC_FP32_BULK = 0, 1
+
+
+class DgError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, status_str(code), code))
+
+
+class dg_mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3)]
+
+
+class dg_av_params(ctypes.Structure):
+    _fields_ = [("enabled", ctypes.c_int), ("scale", ctypes.c_double), ("f_v", ctypes.c_double),
+                ("f_tau", ctypes.c_double), ("f_w", ctypes.c_double), ("s_onset", ctypes.c_double),
+                ("alpha_max", ctypes.c_double)]
+
+
+class dg_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("basis", ctypes.c_int), ("cfl", ctypes.c_double),
+                ("cells_per_block", ctypes.c_int), ("faces_per_block", ctypes.c_int)]
+
+
+_V = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+_SIGS = {
+    "dg_av_defaults": (None, [ctypes.POINTER(dg_av_params)]),
+    "dg_options_defaults": (None, [ctypes.POINTER(dg_options)]),
+    "dg_init": (ctypes.c_int, [ctypes.POINTER(dg_mesh), ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.POINTER(dg_av_params), ctypes.POINTER(dg_options),
+                               ctypes.POINTER(_V)]),
+    "dg_free": (None, [_V]),
+    "dg_state_len": (ctypes.c_size_t, [_V]),
+    "dg_num_fields": (ctypes.c_int, [_V]),
+    "dg_rhs": (ctypes.c_int, [_V, _V, _V, _V]),
+    "dg_step": (ctypes.c_int, [_V, _V, ctypes.c_double, _V]),
+    "dg_step_cfl": (ctypes.c_int, [_V, _V, _V, _V]),
+    "dg_max_dt": (ctypes.c_int, [_V, _V, _D, _D, _D, _V]),
+    "dg_conserved_totals": (ctypes.c_int, [_V, _V, _D, _V]),
+    "dg_set_forcing": (ctypes.c_int, [_V, _V]),
+    "dg_set_sensor_rate": (ctypes.c_int, [_V, _V, _V]),
+    "dg_get_sensor_rate": (ctypes.c_int, [_V, _V, _V]),
+    "dg_check": (ctypes.c_int, [_V, _V]),
+    "dg_get_tiles": (ctypes.c_int, [_V, _I, _I, _I, _I]),
+    "dg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+}
+EXPORTS = tuple(_SIGS)
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdgmi.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(code):
+    try:
+        return lib().dg_status_str(code).decode()
+    except Exception:  # pragma: no cover - library missing
+        return "status"
+
+
+def _chk(code, what):
+    if code != DG_OK:
+        raise DgError(code, what)
+
+
+def _stream(stream):
+    if stream is None:
+        return _V(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return _V(stream.cuda_stream)
+    return _V(stream)
+
+
+def _dptr(t, n=None, writable=False):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError("expected a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError("tensor has %d elements, expected %d" % (t.numel(), n))
+    return _V(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# same-name wrappers of the C entry points
+# ---------------------------------------------------------------------------
+
+def dg_av_defaults():
+    av = dg_av_params()
+    lib().dg_av_defaults(ctypes.byref(av))
+    return av
+
+
+def dg_options_defaults():
+    o = dg_options()
+    lib().dg_options_defaults(ctypes.byref(o))
+    return o
+
+
+def make_mesh(dim, n, lo=None, hi=None, bc=None):
+    m = dg_mesh()
+    m.dim = dim
+    for a in range(3):
+        m.n[a] = n[a] if a < dim else 1
+        m.lo[a] = (lo[a] if lo is not None else 0.0) if a < dim else 0.0
+        m.hi[a] = (hi[a] if hi is not None else 1.0) if a < dim else 1.0
+        m.bc[a] = (bc[a] if bc is not None else DG_BC_PERIODIC) if a < dim else 0
+    return m
+
+
+def dg_init(mesh, order, gamma, nu=0.0, kappa=0.0, av=None, opt=None):
+    ctx = _V()
+    _chk(lib().dg_init(ctypes.byref(mesh), order, gamma, nu, kappa,
+                       ctypes.byref(av) if av is not None else None,
+                       ctypes.byref(opt) if opt is not None else None, ctypes.byref(ctx)), "dg_init")
+    return ctx
+
+
+def dg_free(ctx):
+    lib().dg_free(ctx)
+
+
+def dg_state_len(ctx):
+    return lib().dg_state_len(ctx)
+
+
+def dg_num_fields(ctx):
+    return lib().dg_num_fields(ctx)
+
+
+def dg_rhs(ctx, w, wdot, stream=None):
+    n = dg_state_len(ctx)
+    _chk(lib().dg_rhs(ctx, _dptr(w, n), _dptr(wdot, n), _stream(stream)), "dg_rhs")
+
+
+def dg_step(ctx, w, dt, stream=None):
+    _chk(lib().dg_step(ctx, _dptr(w, dg_state_len(ctx)), float(dt), _stream(stream)), "dg_step")
+
+
+def dg_step_cfl(ctx, w, dt_dev=None, stream=None):
+    p = _dptr(dt_dev, 1) if dt_dev is not None else None
+    _chk(lib().dg_step_cfl(ctx, _dptr(w, dg_state_len(ctx)), p, _stream(stream)), "dg_step_cfl")
+
+
+def dg_max_dt(ctx, w, stream=None):
+    dt, cm, vm = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _chk(lib().dg_max_dt(ctx, _dptr(w, dg_state_len(ctx)), ctypes.byref(dt), ctypes.byref(cm),
+                         ctypes.byref(vm), _stream(stream)), "dg_max_dt")
+    return dt.value, cm.value, vm.value
+
+
+def dg_conserved_totals(ctx, w, dim, stream=None):
+    out = (ctypes.c_double * (dim + 2))()
+    _chk(lib().dg_conserved_totals(ctx, _dptr(w, dg_state_len(ctx)), out, _stream(stream)),
+         "dg_conserved_totals")
+    return list(out)
+
+
+def dg_set_forcing(ctx, s):
+    _chk(lib().dg_set_forcing(ctx, None if s is None else _dptr(s)), "dg_set_forcing")
+
+
+def dg_set_sensor_rate(ctx, R, stream=None):
+    _chk(lib().dg_set_sensor_rate(ctx, _dptr(R), _stream(stream)), "dg_set_sensor_rate")
+
+
+def dg_get_sensor_rate(ctx, R, stream=None):
+    _chk(lib().dg_get_sensor_rate(ctx, _dptr(R), _stream(stream)), "dg_get_sensor_rate")
+
+
+def dg_check(ctx, stream=None):
+    return lib().dg_check(ctx, _stream(stream))
+
+
+def dg_get_tiles(ctx):
+    v = [ctypes.c_int() for _ in range(4)]
+    _chk(lib().dg_get_tiles(ctx, *[ctypes.byref(x) for x in v]), "dg_get_tiles")
+    return tuple(x.value for x in v)
+
+
+# ---------------------------------------------------------------------------
+# convenience object (owns one context)
+# ---------------------------------------------------------------------------
+
+class Solver:
+    """One DG context on the current GPU.
+
+    ``av``: None (off), True (paper defaults) or a dict overriding defaults.
+    ``precision``: "fp64" or "fp32" (FP32 bulk, FP64 state and RK)."""
+
+    def __init__(self, dim, n, order, gamma, nu=0.0, kappa=0.0, lo=None, hi=None, bc=None, av=None,
+                 precision="fp64", cfl=0.5, cells_per_block=0, faces_per_block=0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the DG library runs on the GPU only")
+        self.dim, self.order = dim, order
+        if hi is None:
+            hi = [n[a] / n[0] for a in range(dim)]
+        self.mesh = make_mesh(dim, n, lo, hi, bc)
+        avp = None
+        if av is not None and av is not False:
+            avp = dg_av_defaults()
+            if isinstance(av, dict):
+                for k, v in av.items():
+                    setattr(avp, k, v)
+        opt = dg_options_defaults()
+        opt.precision = DG_PREC_FP64 if precision == "fp64" else DG_PREC_FP32_BULK
+        opt.cfl = cfl
+        opt.cells_per_block = cells_per_block
+        opt.faces_per_block = faces_per_block
+        self.ctx = dg_init(self.mesh, order, gamma, nu, kappa, avp, opt)
+        self.nfields = dg_num_fields(self.ctx)
+        self.ncells = 1
+        for a in range(dim):
+            self.ncells *= n[a]
+        self.nmodes = order ** dim
+        self._forcing = None
+
+    @property
+    def shape(self):
+        return (self.ncells, self.nfields, self.nmodes)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            dg_free(ctx)
+            self.ctx = None
+
+    def rhs(self, w, out=None, stream=None):
+        out = torch.empty_like(w) if out is None else out
+        dg_rhs(self.ctx, w, out, stream)
+        return out
+
+    def step(self, w, dt, stream=None):
+        dg_step(self.ctx, w, dt, stream)
+
+    def step_cfl(self, w, dt_dev=None, stream=None):
+        dg_step_cfl(self.ctx, w, dt_dev, stream)
+
+    def max_dt(self, w, stream=None):
+        return dg_max_dt(self.ctx, w, stream)
+
+    def totals(self, w, stream=None):
+        return dg_conserved_totals(self.ctx, w, self.dim, stream)
+
+    def set_forcing(self, s):
+        self._forcing = s
+        dg_set_forcing(self.ctx, s)
+
+    def set_sensor_rate(self, R, stream=None):
+        dg_set_sensor_rate(self.ctx, R, stream)
+
+    def get_sensor_rate(self, stream=None):
+        R = torch.empty(self.ncells, dtype=torch.float64, device="cuda")
+        dg_get_sensor_rate(self.ctx, R, stream)
+        return R
+
+    def check(self, stream=None):
+        return dg_check(self.ctx, stream)
+
+    def tiles(self):
+        return dg_get_tiles(self.ctx)

@@ -1,0 +1,85 @@
+// dg_common.hpp -- plain structs shared by the host runtime and the HIP
+// kernels of the DG library (argument blocks and per-order tables).
+#pragma once
+#include <stdint.h>
+
+namespace dgk {
+
+constexpr int MAXP = 8;     // highest order (modes / Gauss points per axis)
+constexpr int MAXF = 9;     // stored fields (dim+2, +1 AV) plus dim forcing fields
+
+// Per-order 1D tables on the p Gauss-Legendre nodes x_j of [-1, 1]
+// (Sec. 2.3 scaled Legendre basis, Sec. 2.4 quadrature, Sec. 3.2 recovery).
+template <typename T>
+struct Tab {
+    T B[MAXP][MAXP];    // B[l][j]  = Pt_l(x_j)              modal -> point
+    T Bd[MAXP][MAXP];   // Bd[l][j] = Pt_l'(x_j)             modal -> point derivative
+    T D[MAXP][MAXP];    // D[j][k]  = L_k'(x_j)              collocation derivative
+    T g[MAXP];          // Gauss weights
+    T Lp[MAXP];         // L_j(+1)  Lagrange basis of the nodes at the upper end
+    T Lm[MAXP];         // L_j(-1)
+    T ep[MAXP];         // Pt_m(+1)
+    T em[MAXP];         // Pt_m(-1)
+    T rvL[MAXP];        // recovered face value   = sum_m rvL[m] wL_m + rvR[m] wR_m
+    T rvR[MAXP];        //   (normal mode index m, per transverse mode)
+    T rdL[MAXP];        // recovered d/dxi* at the face (scale by 1/(f h))
+    T rdR[MAXP];
+};
+
+// Physics and discretisation constants of one context (FP64; kernels convert).
+struct Phys {
+    double gamma, nu, kappa, h;
+    double two_over_h;   // 2/h: d/dx = (2/h) d/dxi
+    double inv_fh;       // 1/(f h): d/dx = (1/(f h)) d/dxi* on the recovery domain
+    double pref;         // 2^(1-d)/h: prefactor of volume and surface sums
+    double half_h;       // h/2: converts a source projection to the common prefactor
+    int ns_on;           // nu > 0 or kappa > 0
+    int av_on;           // AV field present
+    double av_scale, f_v, sink;   // sink = p/(f_tau h): alpha/tau = alpha c_s sink
+    double f_w, s_thr, alpha_max, eps_fac;   // s_thr = s_onset/p^2, eps_fac = h/p
+};
+
+// Mesh geometry.  Face space of direction a has nf[a] planes along a
+// (n[a] periodic, n[a]+1 outflow) and n[b] along the other axes.
+struct Geo {
+    int n[3];
+    int nf[3];
+    int bc[3];
+    long long ncells;
+    long long nfaces[3];
+    long long fb_off[3];   // element offset of direction a's block in the face buffer
+};
+
+// Volume/stage kernel.  out = c_base*base + c_cur*cur + c_L*dt*L(cur);
+// optionally out2 = d_x2*x2 + d_cur*cur + d_L*dt*L(cur) (5-stage RK, stage 4).
+struct VolArgs {
+    const double *cur;
+    const double *base;
+    const double *x2;
+    double *out;
+    double *out2;
+    double c_base, c_cur, c_L, d_x2, d_cur, d_L;
+    const double *dt_ptr;   // device dt (used when not null)
+    double dt;
+    const void *fb;         // face fluxes (T), weighted by the transverse Gauss weights
+    const double *forcing;  // [cell][dim][p^d] or null
+    const double *R_prev;   // [cell] dlnS/dt of the previous step (AV) or null
+    double *R_out;          // [cell] dlnS/dt of `cur` (stage 1) or null
+    int *flag;              // error flag: 1 non-physical mean, 2 non-finite
+    int check;              // test the new cell means (RK stages) or not (RHS)
+    int cells_per_block;
+};
+
+struct FaceArgs {
+    const double *w;
+    void *fb;
+    int faces_per_block;
+};
+
+struct CflArgs {
+    const double *w;
+    unsigned long long *maxbits;   // [0] = c_s max, [1] = |v| max (bit patterns)
+    int cells_per_block;
+};
+
+}  // namespace dgk

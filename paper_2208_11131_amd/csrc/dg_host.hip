@@ -1,0 +1,787 @@
+// dg_host.hip -- host runtime of the DG library: C ABI (include/dg.h),
+// per-order tables, buffer management, launch configuration and the SSP-RK
+// stage sequencing.  Also holds the small reduction kernels (CFL finalise,
+// conserved totals).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "dg.h"
+#include "dg_common.hpp"
+#include "dg_registry.hpp"
+
+using dgk::KernelSet;
+using dgk::MAXP;
+using dgk::Tab;
+
+// ---------------------------------------------------------------------------
+// tables (long double on the host, rounded once to FP64 / FP32)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+typedef long double LD;
+
+// Unscaled Legendre P_0..P_lmax at x and derivatives, with
+// P_{l+1} = ((2l+1) x P_l - l P_{l-1})/(l+1) and P'_{l+1} = (l+1) P_l + x P'_l.
+void leg(int lmax, LD x, LD *P, LD *dP)
+{
+    P[0] = 1.0L;
+    dP[0] = 0.0L;
+    for (int l = 0; l < lmax; ++l) {
+        const LD pm = l > 0 ? P[l - 1] : 0.0L;
+        P[l + 1] = ((2 * l + 1) * x * P[l] - l * pm) / (l + 1);
+        dP[l + 1] = (l + 1) * P[l] + x * dP[l];
+    }
+}
+
+// scaled basis Pt_l = sqrt(2l+1) P_l and its derivative
+void sleg(int lmax, LD x, LD *P, LD *dP)
+{
+    leg(lmax, x, P, dP);
+    for (int l = 0; l <= lmax; ++l) {
+        const LD s = sqrtl(2.0L * l + 1.0L);
+        P[l] *= s;
+        dP[l] *= s;
+    }
+}
+
+// n-point Gauss-Legendre nodes (ascending) and weights by Newton iteration.
+void gauss_ld(int n, LD *x, LD *w)
+{
+    LD P[64], dP[64];
+    for (int i = 0; i < n; ++i) {
+        LD z = cosl(3.14159265358979323846264338327950288L * (4.0L * (n - i) - 1.0L) / (4.0L * n + 2.0L));
+        for (int it = 0; it < 60; ++it) {
+            leg(n, z, P, dP);
+            const LD dz = P[n] / dP[n];
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        leg(n, z, P, dP);
+        x[i] = z;
+        w[i] = 2.0L / ((1.0L - z * z) * dP[n] * dP[n]);
+    }
+}
+
+template <typename T>
+void round_tab(const Tab<LD> &s, Tab<T> &d)
+{
+    for (int i = 0; i < MAXP; ++i) {
+        for (int j = 0; j < MAXP; ++j) {
+            d.B[i][j] = (T)s.B[i][j];
+            d.Bd[i][j] = (T)s.Bd[i][j];
+            d.D[i][j] = (T)s.D[i][j];
+        }
+        d.g[i] = (T)s.g[i];
+        d.Lp[i] = (T)s.Lp[i];
+        d.Lm[i] = (T)s.Lm[i];
+        d.ep[i] = (T)s.ep[i];
+        d.em[i] = (T)s.em[i];
+        d.rvL[i] = (T)s.rvL[i];
+        d.rvR[i] = (T)s.rvR[i];
+        d.rdL[i] = (T)s.rdL[i];
+        d.rdR[i] = (T)s.rdR[i];
+    }
+}
+
+// Tables of order P (Sec. 2.3, 2.4, 3.2).
+void build_tab(int P, Tab<LD> &t)
+{
+    memset(&t, 0, sizeof(t));
+    LD x[MAXP], w[MAXP], Pv[64], dPv[64];
+    gauss_ld(P, x, w);
+    for (int j = 0; j < P; ++j) {
+        sleg(P - 1, x[j], Pv, dPv);
+        for (int l = 0; l < P; ++l) {
+            t.B[l][j] = Pv[l];
+            t.Bd[l][j] = dPv[l];
+        }
+        t.g[j] = w[j];
+    }
+    // barycentric weights -> Lagrange derivative matrix and end values
+    LD lam[MAXP];
+    for (int j = 0; j < P; ++j) {
+        LD pr = 1.0L;
+        for (int k = 0; k < P; ++k)
+            if (k != j) pr *= (x[j] - x[k]);
+        lam[j] = 1.0L / pr;
+    }
+    for (int j = 0; j < P; ++j) {
+        LD diag = 0.0L;
+        for (int k = 0; k < P; ++k) {
+            if (k == j) continue;
+            const LD v = (lam[k] / lam[j]) / (x[j] - x[k]);
+            t.D[j][k] = v;
+            diag -= v;
+        }
+        t.D[j][j] = diag;
+        LD lp = 1.0L, lm = 1.0L;
+        for (int k = 0; k < P; ++k) {
+            if (k == j) continue;
+            lp *= (1.0L - x[k]) / (x[j] - x[k]);
+            lm *= (-1.0L - x[k]) / (x[j] - x[k]);
+        }
+        t.Lp[j] = lp;
+        t.Lm[j] = lm;
+    }
+    for (int m = 0; m < P; ++m) {
+        t.ep[m] = sqrtl(2.0L * m + 1.0L);
+        t.em[m] = (m & 1 ? -1.0L : 1.0L) * sqrtl(2.0L * m + 1.0L);
+    }
+    // Recovery (Sec. 3.2): projection of the two sides onto the normal
+    // Legendre polynomials of degree 0..n+1 on K* (xi* in [-1,1], overlap f),
+    //   A_side(la, m) = (1/2) int_half Pt_la(xi*) Pt_m(2 f xi* +- 1) dxi*,
+    // then value / xi*-derivative of the recovered expansion at xi* = 0.
+    const LD f = (P - 1) <= 2 ? 0.75L : 1.0L;
+    LD xq[24], wq[24], P0[64], dP0[64];
+    gauss_ld(20, xq, wq);
+    sleg(P, 0.0L, P0, dP0);
+    for (int m = 0; m < P; ++m) {
+        LD vl = 0, vr = 0, dl = 0, dr = 0;
+        for (int la = 0; la <= P; ++la) {
+            LD AL = 0, AR = 0;
+            for (int q = 0; q < 20; ++q) {
+                LD a[64], da[64], b[64], db[64];
+                const LD xsL = 0.5L * (xq[q] - 1.0L);   // [-1, 0]
+                const LD xsR = 0.5L * (xq[q] + 1.0L);   // [0, 1]
+                sleg(P, xsL, a, da);
+                sleg(P - 1, 2.0L * f * xsL + 1.0L, b, db);
+                AL += 0.5L * wq[q] * 0.5L * a[la] * b[m];
+                sleg(P, xsR, a, da);
+                sleg(P - 1, 2.0L * f * xsR - 1.0L, b, db);
+                AR += 0.5L * wq[q] * 0.5L * a[la] * b[m];
+            }
+            vl += AL * P0[la];
+            vr += AR * P0[la];
+            dl += AL * dP0[la];
+            dr += AR * dP0[la];
+        }
+        t.rvL[m] = vl;
+        t.rvR[m] = vr;
+        t.rdL[m] = dl;
+        t.rdR[m] = dr;
+    }
+}
+
+struct Tables {
+    Tab<double> d[MAXP + 1];
+    Tab<float> f[MAXP + 1];
+};
+
+Tables *g_tables = nullptr;
+std::mutex g_mu;
+unsigned long long g_uploaded = 0;   // bit mask of devices with tables
+
+dg_status ensure_tables(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_tables) {
+        Tables *t = new (std::nothrow) Tables;
+        if (!t) return DG_ENOMEM;
+        memset(t, 0, sizeof(*t));
+        for (int P = 1; P <= MAXP; ++P) {
+            Tab<LD> s;
+            build_tab(P, s);
+            round_tab(s, t->d[P]);
+            round_tab(s, t->f[P]);
+        }
+        g_tables = t;
+    }
+    if (dev < 64 && (g_uploaded >> dev) & 1ULL) return DG_OK;
+    if (dgk::dgk_upload_2d_f64(g_tables->d, g_tables->f) || dgk::dgk_upload_3d_f64(g_tables->d, g_tables->f) ||
+        dgk::dgk_upload_2d_f32(g_tables->d, g_tables->f) || dgk::dgk_upload_3d_f32(g_tables->d, g_tables->f))
+        return DG_EDEVICE;
+    if (dev < 64) g_uploaded |= 1ULL << dev;
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+
+__global__ void cfl_finalize(unsigned long long *bits, double *res, double *dt_copy, double num)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double cm = __longlong_as_double((long long)bits[0]);
+        const double vm = __longlong_as_double((long long)bits[1]);
+        const double dt = num / (cm + vm);
+        res[0] = dt;
+        res[1] = cm;
+        res[2] = vm;
+        if (dt_copy) dt_copy[0] = dt;
+        bits[0] = 0ULL;
+        bits[1] = 0ULL;
+    }
+}
+
+// Neumaier-compensated add of x into (s, c).
+__device__ __forceinline__ void nadd(double &s, double &c, double x)
+{
+    const double t = s + x;
+    if (fabs(s) >= fabs(x))
+        c += (s - t) + x;
+    else
+        c += (x - t) + s;
+    s = t;
+}
+
+// Per-block compensated partial sums of |K| w_0 over a contiguous cell range
+// (fixed thread/cell assignment and combination order: deterministic).
+__global__ void totals_partial(const double *w, long long NC, int F, int NP, int Fc, double vol, int chunk,
+                               double *part)
+{
+    __shared__ double ss[256 * 5], cc[256 * 5];
+    const long long c0 = (long long)blockIdx.x * chunk;
+    const int tid = threadIdx.x;
+    for (int f = 0; f < Fc; ++f) {
+        double s = 0.0, c = 0.0;
+        for (long long k = c0 + tid; k < c0 + chunk && k < NC; k += blockDim.x)
+            nadd(s, c, vol * w[(k * F + f) * (long long)NP]);
+        ss[f * 256 + tid] = s;
+        cc[f * 256 + tid] = c;
+    }
+    __syncthreads();
+    if (tid < Fc) {
+        double s = 0.0, c = 0.0;
+        for (int t = 0; t < (int)blockDim.x; ++t) {
+            nadd(s, c, ss[tid * 256 + t]);
+            c += cc[tid * 256 + t];
+        }
+        part[(blockIdx.x * Fc + tid) * 2] = s;
+        part[(blockIdx.x * Fc + tid) * 2 + 1] = c;
+    }
+}
+
+__global__ void totals_final(const double *part, int nblk, int Fc, double *out)
+{
+    const int f = threadIdx.x;
+    if (f < Fc) {
+        double s = 0.0, c = 0.0;
+        for (int b = 0; b < nblk; ++b) {
+            nadd(s, c, part[(b * Fc + f) * 2]);
+            c += part[(b * Fc + f) * 2 + 1];
+        }
+        out[f] = s + c;
+    }
+}
+
+int roundup(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+struct dg_ctx {
+    int dim, P, F, Fc, NP, K;
+    long long ncells;
+    dgk::Phys ph;
+    dgk::Geo geo;
+    int precision;
+    double cfl;
+    int device;
+    bool grad;
+    KernelSet ks, ks64;
+    int vol_C, vol_T, face_C, face_T, cfl_C, cfl_T;
+    size_t vol_lds, vol_lds_forced, face_lds, cfl_lds;
+    int stages;
+    double *reg[3];
+    void *fb;
+    size_t fb_bytes;
+    double *R[2];
+    int rpar;
+    unsigned long long *maxbits;   // [2]
+    double *scal;                  // [0] dt, [1] cmax, [2] vmax, [3..] totals
+    int *flag;
+    double *tot_part;
+    int tot_blocks, tot_chunk;
+    const double *forcing;
+};
+
+namespace {
+
+bool ok(hipError_t e) { return e == hipSuccess; }
+
+void free_bufs(dg_ctx *c)
+{
+    for (int i = 0; i < 3; ++i)
+        if (c->reg[i]) (void)hipFree(c->reg[i]);
+    if (c->fb) (void)hipFree(c->fb);
+    for (int i = 0; i < 2; ++i)
+        if (c->R[i]) (void)hipFree(c->R[i]);
+    if (c->maxbits) (void)hipFree(c->maxbits);
+    if (c->scal) (void)hipFree(c->scal);
+    if (c->flag) (void)hipFree(c->flag);
+    if (c->tot_part) (void)hipFree(c->tot_part);
+}
+
+void get_kernels(int dim, int prec, int P, bool grad, KernelSet *k)
+{
+    if (dim == 2)
+        (prec == DG_PREC_FP64 ? dgk::dgk_get_2d_f64 : dgk::dgk_get_2d_f32)(P, grad, k);
+    else
+        (prec == DG_PREC_FP64 ? dgk::dgk_get_3d_f64 : dgk::dgk_get_3d_f32)(P, grad, k);
+}
+
+constexpr size_t LDS_MAX = 160 * 1024;
+
+dg_status launch(const void *fn, dim3 grid, dim3 block, void **args, size_t lds, hipStream_t s)
+{
+    if (grid.x == 0) return DG_OK;
+    if (!ok(hipLaunchKernel(fn, grid, block, args, lds, s))) return DG_EDEVICE;
+    return DG_OK;
+}
+
+// One RHS evaluation of `in` followed by the stage combination of VolArgs.
+dg_status stage(dg_ctx *c, dgk::VolArgs va, hipStream_t s)
+{
+    dgk::FaceArgs fa;
+    fa.w = va.cur;
+    fa.fb = c->fb;
+    fa.faces_per_block = c->face_C;
+    long long maxf = 0;
+    for (int a = 0; a < c->dim; ++a)
+        if (c->geo.nfaces[a] > maxf) maxf = c->geo.nfaces[a];
+    void *fargs[] = {&c->ph, &c->geo, &fa};
+    dim3 fg((unsigned)((maxf + c->face_C - 1) / c->face_C), (unsigned)c->dim);
+    dg_status st = launch(c->ks.face, fg, dim3(c->face_T), fargs, c->face_lds, s);
+    if (st != DG_OK) return st;
+    va.fb = c->fb;
+    va.forcing = c->forcing;
+    va.flag = c->flag;
+    va.cells_per_block = c->vol_C;
+    void *vargs[] = {&c->ph, &c->geo, &va};
+    dim3 vg((unsigned)((c->ncells + c->vol_C - 1) / c->vol_C));
+    return launch(c->ks.vol, vg, dim3(c->vol_T), vargs, c->forcing ? c->vol_lds_forced : c->vol_lds, s);
+}
+
+dgk::VolArgs blank_args()
+{
+    dgk::VolArgs v;
+    memset(&v, 0, sizeof(v));
+    return v;
+}
+
+dg_status run_cfl(dg_ctx *c, const double *w, double *dt_copy, hipStream_t s)
+{
+    dgk::CflArgs ca;
+    ca.w = w;
+    ca.maxbits = c->maxbits;
+    ca.cells_per_block = c->cfl_C;
+    void *args[] = {&c->ph, &c->geo, &ca};
+    dim3 g((unsigned)((c->ncells + c->cfl_C - 1) / c->cfl_C));
+    dg_status st = launch(c->ks64.cfl, g, dim3(c->cfl_T), args, c->cfl_lds, s);
+    if (st != DG_OK) return st;
+    const double num = c->cfl * c->ph.h / (2.0 * c->P);
+    hipLaunchKernelGGL(cfl_finalize, dim3(1), dim3(64), 0, s, c->maxbits, c->scal, dt_copy, num);
+    return ok(hipGetLastError()) ? DG_OK : DG_EDEVICE;
+}
+
+// SSP-RK step in Shu-Osher form; dt from the host value or a device pointer.
+dg_status rk_step(dg_ctx *c, double *w, double dt, const double *dt_dev, hipStream_t s)
+{
+    double *r1 = c->reg[0], *r2 = c->reg[1], *r3 = c->reg[2];
+    const double *Rp = c->ph.av_on ? c->R[c->rpar] : nullptr;
+    double *Rn = c->ph.av_on ? c->R[c->rpar ^ 1] : nullptr;
+    auto A = [&](const double *cur, const double *base, double *out, double cb, double cc, double cl) {
+        dgk::VolArgs v = blank_args();
+        v.cur = cur;
+        v.base = base;
+        v.out = out;
+        v.c_base = cb;
+        v.c_cur = cc;
+        v.c_L = cl;
+        v.dt = dt;
+        v.dt_ptr = dt_dev;
+        v.R_prev = Rp;
+        v.check = 1;
+        return v;
+    };
+    dg_status st = DG_OK;
+    switch (c->stages) {
+    case 1: {
+        dgk::VolArgs v = A(w, nullptr, w, 0.0, 1.0, 1.0);
+        v.R_out = Rn;
+        st = stage(c, v, s);
+        break;
+    }
+    case 2: {
+        dgk::VolArgs v = A(w, nullptr, r1, 0.0, 1.0, 1.0);
+        v.R_out = Rn;
+        if ((st = stage(c, v, s)) != DG_OK) break;
+        st = stage(c, A(r1, w, w, 0.5, 0.5, 0.5), s);
+        break;
+    }
+    case 3: {
+        dgk::VolArgs v = A(w, nullptr, r1, 0.0, 1.0, 1.0);
+        v.R_out = Rn;
+        if ((st = stage(c, v, s)) != DG_OK) break;
+        if ((st = stage(c, A(r1, w, r2, 0.75, 0.25, 0.25), s)) != DG_OK) break;
+        st = stage(c, A(r2, w, w, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0), s);
+        break;
+    }
+    default: {
+        // SSPRK(5,4), Spiteri & Ruuth (2002), Shu-Osher coefficients
+        dgk::VolArgs v = A(w, nullptr, r1, 0.0, 1.0, 0.391752226571890);
+        v.R_out = Rn;
+        if ((st = stage(c, v, s)) != DG_OK) break;
+        if ((st = stage(c, A(r1, w, r2, 0.444370493651235, 0.555629506348765, 0.368410593050371), s)) != DG_OK)
+            break;
+        if ((st = stage(c, A(r2, w, r3, 0.620101851488403, 0.379898148511597, 0.251891774271694), s)) != DG_OK)
+            break;
+        // u4 -> r1 and the partial sum of the last stage -> w
+        v = A(r3, w, r1, 0.178079954393132, 0.821920045606868, 0.544974750228521);
+        v.out2 = w;
+        v.x2 = r2;
+        v.d_x2 = 0.517231671970585;
+        v.d_cur = 0.096059710526147;
+        v.d_L = 0.063692468666290;
+        if ((st = stage(c, v, s)) != DG_OK) break;
+        st = stage(c, A(r1, w, w, 1.0, 0.386708617503269, 0.226007483236906), s);
+        break;
+    }
+    }
+    if (st == DG_OK && c->ph.av_on) c->rpar ^= 1;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dg_av_defaults(dg_av_params *av)
+{
+    if (!av) return;
+    av->enabled = 1;
+    av->scale = 1.0;
+    av->f_v = 2.5;
+    av->f_tau = 0.5;
+    av->f_w = 0.2;
+    av->s_onset = 1e-4;
+    av->alpha_max = 1.0;
+}
+
+void dg_options_defaults(dg_options *opt)
+{
+    if (!opt) return;
+    opt->precision = DG_PREC_FP64;
+    opt->basis = 0;
+    opt->cfl = 0.5;
+    opt->cells_per_block = 0;
+    opt->faces_per_block = 0;
+}
+
+const char *dg_status_str(dg_status s)
+{
+    switch (s) {
+    case DG_OK: return "ok";
+    case DG_EINVAL: return "invalid argument";
+    case DG_ENOMEM: return "out of device memory";
+    case DG_EDEVICE: return "HIP device or launch error";
+    case DG_ENONPHYSICAL: return "non-positive cell-mean density or pressure";
+    case DG_ENONFINITE: return "non-finite weight";
+    case DG_EUNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, double kappa, const dg_av_params *av,
+                  const dg_options *opt, dg_ctx **out)
+{
+    if (!out) return DG_EINVAL;
+    *out = nullptr;
+    if (!mesh || (mesh->dim != 2 && mesh->dim != 3) || order < 1 || order > MAXP) return DG_EINVAL;
+    if (!(gamma > 1.0) || !(nu >= 0.0) || !(kappa >= 0.0) || !std::isfinite(nu) || !std::isfinite(kappa))
+        return DG_EINVAL;
+    dg_options o;
+    dg_options_defaults(&o);
+    if (opt) o = *opt;
+    if (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_BULK) return DG_EINVAL;
+    if (o.basis != 0) return DG_EUNSUPPORTED;
+    if (!(o.cfl > 0.0) || o.cells_per_block < 0 || o.faces_per_block < 0) return DG_EINVAL;
+    const int d = mesh->dim;
+    double h = 0.0;
+    for (int a = 0; a < d; ++a) {
+        if (mesh->n[a] < 1 || !(mesh->hi[a] > mesh->lo[a])) return DG_EINVAL;
+        if (mesh->bc[a] != DG_BC_PERIODIC && mesh->bc[a] != DG_BC_OUTFLOW) return DG_EINVAL;
+        const double ha = (mesh->hi[a] - mesh->lo[a]) / mesh->n[a];
+        if (a == 0)
+            h = ha;
+        else if (fabs(ha - h) > 1e-12 * h)
+            return DG_EINVAL;
+    }
+    const bool av_on = av && av->enabled;
+    if (av_on && (!(av->f_tau > 0.0) || !(av->alpha_max >= 0.0) || !(av->scale >= 0.0) || !(av->f_v >= 0.0) ||
+                  !(av->f_w >= 0.0) || !(av->s_onset >= 0.0)))
+        return DG_EINVAL;
+
+    int dev = 0;
+    if (!ok(hipGetDevice(&dev))) return DG_EDEVICE;
+    dg_status st = ensure_tables(dev);
+    if (st != DG_OK) return st;
+
+    dg_ctx *c = new (std::nothrow) dg_ctx;
+    if (!c) return DG_ENOMEM;
+    memset(c, 0, sizeof(*c));
+    c->dim = d;
+    c->P = order;
+    c->Fc = d + 2;
+    c->F = c->Fc + (av_on ? 1 : 0);
+    c->NP = 1;
+    for (int a = 0; a < d; ++a) c->NP *= order;
+    c->K = c->NP / order;
+    c->device = dev;
+    c->precision = o.precision;
+    c->cfl = o.cfl;
+    c->stages = order == 1 ? 1 : order == 2 ? 2 : order == 3 ? 3 : 5;
+
+    dgk::Geo &g = c->geo;
+    c->ncells = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = a < d ? mesh->n[a] : 1;
+        g.bc[a] = a < d ? mesh->bc[a] : 0;
+        g.nf[a] = g.n[a] + (g.bc[a] == DG_BC_OUTFLOW ? 1 : 0);
+        c->ncells *= g.n[a];
+    }
+    g.ncells = c->ncells;
+    long long off = 0;
+    for (int a = 0; a < 3; ++a) {
+        long long nfc = 0;
+        if (a < d) {
+            nfc = 1;
+            for (int b = 0; b < 3; ++b) nfc *= (b == a) ? g.nf[b] : g.n[b];
+        }
+        g.nfaces[a] = nfc;
+        g.fb_off[a] = off;
+        off += nfc * c->Fc * c->K;
+    }
+    const size_t tsz = c->precision == DG_PREC_FP64 ? sizeof(double) : sizeof(float);
+    c->fb_bytes = (size_t)off * tsz;
+
+    dgk::Phys &ph = c->ph;
+    ph.gamma = gamma;
+    ph.nu = nu;
+    ph.kappa = kappa;
+    ph.h = h;
+    ph.two_over_h = 2.0 / h;
+    const double fr = (order - 1) <= 2 ? 0.75 : 1.0;
+    ph.inv_fh = 1.0 / (fr * h);
+    ph.pref = std::pow(2.0, 1 - d) / h;
+    ph.half_h = 0.5 * h;
+    ph.ns_on = (nu > 0.0 || kappa > 0.0) ? 1 : 0;
+    ph.av_on = av_on ? 1 : 0;
+    if (av_on) {
+        ph.av_scale = av->scale;
+        ph.f_v = av->f_v;
+        ph.sink = order / (av->f_tau * h);
+        ph.f_w = av->f_w;
+        ph.s_thr = av->s_onset / ((double)order * order);
+        ph.alpha_max = av->alpha_max;
+        ph.eps_fac = h / order;
+    }
+    c->grad = ph.ns_on || ph.av_on;
+    get_kernels(d, c->precision, order, c->grad, &c->ks);
+    get_kernels(d, DG_PREC_FP64, order, c->grad, &c->ks64);
+    if (!c->ks.vol || !c->ks.face || !c->ks64.cfl) {
+        delete c;
+        return DG_EUNSUPPORTED;
+    }
+
+    // launch tiles: about 256 volume points / 128 face points per block
+    const int Fx = c->F + d;
+    if (o.cells_per_block > 0)
+        c->vol_C = o.cells_per_block;
+    else
+        c->vol_C = std::max(1, 256 / c->NP);
+    while (c->vol_C > 1 && c->ks.vol_lds(c->vol_C, c->F, Fx) > LDS_MAX) --c->vol_C;
+    c->vol_T = std::min(512, std::max(64, roundup(c->vol_C * c->NP, 64)));
+    c->vol_lds = c->ks.vol_lds(c->vol_C, c->F, c->F);
+    c->vol_lds_forced = c->ks.vol_lds(c->vol_C, c->F, Fx);
+    if (c->vol_lds > LDS_MAX) {
+        delete c;
+        return DG_EUNSUPPORTED;
+    }
+    if (o.faces_per_block > 0)
+        c->face_C = o.faces_per_block;
+    else
+        c->face_C = std::max(1, 128 / c->K);
+    while (c->face_C > 1 && c->ks.face_lds(c->face_C, c->F) > 64 * 1024) --c->face_C;
+    c->face_T = std::min(512, std::max(64, roundup(c->face_C * c->K, 64)));
+    c->face_lds = c->ks.face_lds(c->face_C, c->F);
+    c->cfl_C = std::max(1, 256 / c->NP);
+    c->cfl_T = 256;
+    while (c->cfl_C > 1 && c->ks64.cfl_lds(c->cfl_C, c->cfl_T) > 64 * 1024) --c->cfl_C;
+    c->cfl_lds = c->ks64.cfl_lds(c->cfl_C, c->cfl_T);
+    if (c->face_lds > LDS_MAX || c->cfl_lds > LDS_MAX) {
+        delete c;
+        return DG_EUNSUPPORTED;
+    }
+    const size_t lim = LDS_MAX;
+    (void)hipFuncSetAttribute(c->ks.vol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+    (void)hipFuncSetAttribute(c->ks.face, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+    (void)hipFuncSetAttribute(c->ks64.cfl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+
+    // buffers
+    const size_t nstate = (size_t)c->ncells * c->F * c->NP;
+    const int nreg = c->stages == 1 ? 0 : c->stages == 2 ? 1 : c->stages == 3 ? 2 : 3;
+    bool good = true;
+    for (int i = 0; i < nreg && good; ++i) good = ok(hipMalloc(&c->reg[i], nstate * sizeof(double)));
+    good = good && ok(hipMalloc(&c->fb, c->fb_bytes > 0 ? c->fb_bytes : 16));
+    if (av_on)
+        for (int i = 0; i < 2 && good; ++i) {
+            good = ok(hipMalloc(&c->R[i], c->ncells * sizeof(double)));
+            good = good && ok(hipMemset(c->R[i], 0, c->ncells * sizeof(double)));
+        }
+    good = good && ok(hipMalloc(&c->maxbits, 2 * sizeof(unsigned long long)));
+    good = good && ok(hipMemset(c->maxbits, 0, 2 * sizeof(unsigned long long)));
+    good = good && ok(hipMalloc(&c->scal, 16 * sizeof(double)));
+    good = good && ok(hipMalloc(&c->flag, sizeof(int)));
+    good = good && ok(hipMemset(c->flag, 0, sizeof(int)));
+    c->tot_chunk = 4096;
+    c->tot_blocks = (int)((c->ncells + c->tot_chunk - 1) / c->tot_chunk);
+    good = good && ok(hipMalloc(&c->tot_part, (size_t)c->tot_blocks * c->Fc * 2 * sizeof(double)));
+    if (!good) {
+        free_bufs(c);
+        delete c;
+        (void)hipGetLastError();
+        return DG_ENOMEM;
+    }
+    if (!ok(hipDeviceSynchronize())) {
+        free_bufs(c);
+        delete c;
+        return DG_EDEVICE;
+    }
+    *out = c;
+    return DG_OK;
+}
+
+void dg_free(dg_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    free_bufs(ctx);
+    delete ctx;
+}
+
+size_t dg_state_len(const dg_ctx *c) { return c ? (size_t)c->ncells * c->F * c->NP : 0; }
+
+int dg_num_fields(const dg_ctx *c) { return c ? c->F : 0; }
+
+dg_status dg_rhs(dg_ctx *c, const double *w, double *wdot, void *stream)
+{
+    if (!c || !w || !wdot || w == wdot) return DG_EINVAL;
+    dgk::VolArgs v = blank_args();
+    v.cur = w;
+    v.out = wdot;
+    v.c_L = 1.0;
+    v.dt = 1.0;
+    v.R_prev = c->ph.av_on ? c->R[c->rpar] : nullptr;
+    v.check = 0;
+    return stage(c, v, (hipStream_t)stream);
+}
+
+dg_status dg_step(dg_ctx *c, double *w, double dt, void *stream)
+{
+    if (!c || !w || !(dt > 0.0) || !std::isfinite(dt)) return DG_EINVAL;
+    return rk_step(c, w, dt, nullptr, (hipStream_t)stream);
+}
+
+dg_status dg_step_cfl(dg_ctx *c, double *w, double *dt_dev, void *stream)
+{
+    if (!c || !w) return DG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    dg_status st = run_cfl(c, w, dt_dev, s);
+    if (st != DG_OK) return st;
+    return rk_step(c, w, 0.0, c->scal, s);
+}
+
+dg_status dg_max_dt(dg_ctx *c, const double *w, double *dt_out, double *cmax_out, double *vmax_out, void *stream)
+{
+    if (!c || !w || !dt_out) return DG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    dg_status st = run_cfl(c, w, nullptr, s);
+    if (st != DG_OK) return st;
+    double res[3];
+    if (!ok(hipMemcpyAsync(res, c->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s))) return DG_EDEVICE;
+    if (!ok(hipStreamSynchronize(s))) return DG_EDEVICE;
+    *dt_out = res[0];
+    if (cmax_out) *cmax_out = res[1];
+    if (vmax_out) *vmax_out = res[2];
+    return DG_OK;
+}
+
+dg_status dg_conserved_totals(dg_ctx *c, const double *w, double *out, void *stream)
+{
+    if (!c || !w || !out) return DG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    double vol = 1.0;
+    for (int a = 0; a < c->dim; ++a) vol *= c->ph.h;
+    hipLaunchKernelGGL(totals_partial, dim3(c->tot_blocks), dim3(256), 0, s, w, c->ncells, c->F, c->NP, c->Fc, vol,
+                       c->tot_chunk, c->tot_part);
+    hipLaunchKernelGGL(totals_final, dim3(1), dim3(64), 0, s, c->tot_part, c->tot_blocks, c->Fc, c->scal + 3);
+    if (!ok(hipGetLastError())) return DG_EDEVICE;
+    if (!ok(hipMemcpyAsync(out, c->scal + 3, c->Fc * sizeof(double), hipMemcpyDeviceToHost, s))) return DG_EDEVICE;
+    if (!ok(hipStreamSynchronize(s))) return DG_EDEVICE;
+    return DG_OK;
+}
+
+dg_status dg_set_forcing(dg_ctx *c, const double *s_coeffs)
+{
+    if (!c) return DG_EINVAL;
+    if (s_coeffs && c->vol_lds_forced > LDS_MAX) return DG_EUNSUPPORTED;
+    c->forcing = s_coeffs;
+    return DG_OK;
+}
+
+dg_status dg_set_sensor_rate(dg_ctx *c, const double *R, void *stream)
+{
+    if (!c || !R || !c->ph.av_on) return DG_EINVAL;
+    if (!ok(hipMemcpyAsync(c->R[c->rpar], R, c->ncells * sizeof(double), hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream)))
+        return DG_EDEVICE;
+    return DG_OK;
+}
+
+dg_status dg_get_sensor_rate(dg_ctx *c, double *R, void *stream)
+{
+    if (!c || !R || !c->ph.av_on) return DG_EINVAL;
+    if (!ok(hipMemcpyAsync(R, c->R[c->rpar], c->ncells * sizeof(double), hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream)))
+        return DG_EDEVICE;
+    return DG_OK;
+}
+
+dg_status dg_check(dg_ctx *c, void *stream)
+{
+    if (!c) return DG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int f = 0;
+    if (!ok(hipMemcpyAsync(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost, s))) return DG_EDEVICE;
+    if (!ok(hipStreamSynchronize(s))) return DG_EDEVICE;
+    if (f) {
+        if (!ok(hipMemsetAsync(c->flag, 0, sizeof(int), s))) return DG_EDEVICE;
+        if (!ok(hipStreamSynchronize(s))) return DG_EDEVICE;
+    }
+    if (f & 2) return DG_ENONFINITE;
+    if (f & 1) return DG_ENONPHYSICAL;
+    return DG_OK;
+}
+
+dg_status dg_get_tiles(const dg_ctx *c, int *vol_cells, int *vol_threads, int *face_cells, int *face_threads)
+{
+    if (!c) return DG_EINVAL;
+    if (vol_cells) *vol_cells = c->vol_C;
+    if (vol_threads) *vol_threads = c->vol_T;
+    if (face_cells) *face_cells = c->face_C;
+    if (face_threads) *face_threads = c->face_T;
+    return DG_OK;
+}
+
+}  // extern "C"
