@@ -156,6 +156,16 @@ dg_status dg_check(dg_ctx *ctx, void *stream);
 dg_status dg_get_tiles(const dg_ctx *ctx, int *vol_cells, int *vol_threads, int *face_cells,
                        int *face_threads);
 
+/* Kernel timing (instrumentation): when enabled, every face, volume and CFL
+ * kernel launch of this context is bracketed by HIP events recorded on its
+ * stream.  dg_timing_read synchronises on the last event, returns the summed
+ * device milliseconds and launch counts per kernel kind since the last read
+ * (host pointers, any may be NULL) and resets them.  At most 16384 launches
+ * are recorded between reads; later ones are counted in *dropped. */
+dg_status dg_timing_enable(dg_ctx *ctx, int on);
+dg_status dg_timing_read(dg_ctx *ctx, double *face_ms, long long *face_n, double *vol_ms, long long *vol_n,
+                         double *cfl_ms, long long *cfl_n, long long *dropped);
+
 const char *dg_status_str(dg_status s);
 
 #ifdef __cplusplus

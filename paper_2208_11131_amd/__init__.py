@@ -64,6 +64,10 @@ _SIGS = {
     "dg_get_sensor_rate": (ctypes.c_int, [_V, _V, _V]),
     "dg_check": (ctypes.c_int, [_V, _V]),
     "dg_get_tiles": (ctypes.c_int, [_V, _I, _I, _I, _I]),
+    "dg_timing_enable": (ctypes.c_int, [_V, ctypes.c_int]),
+    "dg_timing_read": (ctypes.c_int, [_V, _D, ctypes.POINTER(ctypes.c_longlong), _D,
+                                      ctypes.POINTER(ctypes.c_longlong), _D, ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_longlong)]),
     "dg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
 }
 EXPORTS = tuple(_SIGS)
@@ -210,6 +214,21 @@ def dg_get_tiles(ctx):
     v = [ctypes.c_int() for _ in range(4)]
     _chk(lib().dg_get_tiles(ctx, *[ctypes.byref(x) for x in v]), "dg_get_tiles")
     return tuple(x.value for x in v)
+
+
+def dg_timing_enable(ctx, on=True):
+    _chk(lib().dg_timing_enable(ctx, 1 if on else 0), "dg_timing_enable")
+
+
+def dg_timing_read(ctx):
+    """{'face': (ms, n), 'vol': (ms, n), 'cfl': (ms, n), 'dropped': k}; synchronises."""
+    d = [ctypes.c_double() for _ in range(3)]
+    n = [ctypes.c_longlong() for _ in range(4)]
+    _chk(lib().dg_timing_read(ctx, ctypes.byref(d[0]), ctypes.byref(n[0]), ctypes.byref(d[1]),
+                              ctypes.byref(n[1]), ctypes.byref(d[2]), ctypes.byref(n[2]),
+                              ctypes.byref(n[3])), "dg_timing_read")
+    return {"face": (d[0].value, n[0].value), "vol": (d[1].value, n[1].value),
+            "cfl": (d[2].value, n[2].value), "dropped": n[3].value}
 
 
 # ---------------------------------------------------------------------------

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "dg.h"
 #include "dg_common.hpp"
@@ -303,6 +304,11 @@ struct dg_ctx {
     double *tot_part;
     int tot_blocks, tot_chunk;
     const double *forcing;
+    // kernel timing
+    int timing;
+    std::vector<hipEvent_t> *ev_pool;
+    std::vector<int> *ev_kind;     // per recorded pair: 0 face, 1 vol, 2 cfl
+    long long ev_used, ev_dropped;
 };
 
 namespace {
@@ -332,10 +338,33 @@ void get_kernels(int dim, int prec, int P, bool grad, KernelSet *k)
 
 constexpr size_t LDS_MAX = 160 * 1024;
 
-dg_status launch(const void *fn, dim3 grid, dim3 block, void **args, size_t lds, hipStream_t s)
+constexpr long long EV_MAX = 16384;
+
+// Launch a kernel; with timing on, bracket it by a pair of events.
+dg_status launch(dg_ctx *c, int kind, const void *fn, dim3 grid, dim3 block, void **args, size_t lds,
+                 hipStream_t s)
 {
     if (grid.x == 0) return DG_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c && c->timing) {
+        if (c->ev_used < EV_MAX) {
+            const size_t need = 2 * (size_t)(c->ev_used + 1);
+            while (c->ev_pool->size() < need) {
+                hipEvent_t e;
+                if (!ok(hipEventCreate(&e))) return DG_EDEVICE;
+                c->ev_pool->push_back(e);
+            }
+            e0 = (*c->ev_pool)[2 * c->ev_used];
+            e1 = (*c->ev_pool)[2 * c->ev_used + 1];
+            c->ev_kind->push_back(kind);
+            ++c->ev_used;
+            if (!ok(hipEventRecord(e0, s))) return DG_EDEVICE;
+        } else {
+            ++c->ev_dropped;
+        }
+    }
     if (!ok(hipLaunchKernel(fn, grid, block, args, lds, s))) return DG_EDEVICE;
+    if (e1 && !ok(hipEventRecord(e1, s))) return DG_EDEVICE;
     return DG_OK;
 }
 
@@ -351,7 +380,7 @@ dg_status stage(dg_ctx *c, dgk::VolArgs va, hipStream_t s)
         if (c->geo.nfaces[a] > maxf) maxf = c->geo.nfaces[a];
     void *fargs[] = {&c->ph, &c->geo, &fa};
     dim3 fg((unsigned)((maxf + c->face_C - 1) / c->face_C), (unsigned)c->dim);
-    dg_status st = launch(c->ks.face, fg, dim3(c->face_T), fargs, c->face_lds, s);
+    dg_status st = launch(c, 0, c->ks.face, fg, dim3(c->face_T), fargs, c->face_lds, s);
     if (st != DG_OK) return st;
     va.fb = c->fb;
     va.forcing = c->forcing;
@@ -359,7 +388,7 @@ dg_status stage(dg_ctx *c, dgk::VolArgs va, hipStream_t s)
     va.cells_per_block = c->vol_C;
     void *vargs[] = {&c->ph, &c->geo, &va};
     dim3 vg((unsigned)((c->ncells + c->vol_C - 1) / c->vol_C));
-    return launch(c->ks.vol, vg, dim3(c->vol_T), vargs, c->forcing ? c->vol_lds_forced : c->vol_lds, s);
+    return launch(c, 1, c->ks.vol, vg, dim3(c->vol_T), vargs, c->forcing ? c->vol_lds_forced : c->vol_lds, s);
 }
 
 dgk::VolArgs blank_args()
@@ -377,7 +406,7 @@ dg_status run_cfl(dg_ctx *c, const double *w, double *dt_copy, hipStream_t s)
     ca.cells_per_block = c->cfl_C;
     void *args[] = {&c->ph, &c->geo, &ca};
     dim3 g((unsigned)((c->ncells + c->cfl_C - 1) / c->cfl_C));
-    dg_status st = launch(c->ks64.cfl, g, dim3(c->cfl_T), args, c->cfl_lds, s);
+    dg_status st = launch(c, 2, c->ks64.cfl, g, dim3(c->cfl_T), args, c->cfl_lds, s);
     if (st != DG_OK) return st;
     const double num = c->cfl * c->ph.h / (2.0 * c->P);
     hipLaunchKernelGGL(cfl_finalize, dim3(1), dim3(64), 0, s, c->maxbits, c->scal, dt_copy, num);
@@ -667,7 +696,53 @@ void dg_free(dg_ctx *ctx)
     if (!ctx) return;
     (void)hipDeviceSynchronize();
     free_bufs(ctx);
+    if (ctx->ev_pool) {
+        for (hipEvent_t e : *ctx->ev_pool) (void)hipEventDestroy(e);
+        delete ctx->ev_pool;
+    }
+    delete ctx->ev_kind;
     delete ctx;
+}
+
+dg_status dg_timing_enable(dg_ctx *c, int on)
+{
+    if (!c) return DG_EINVAL;
+    if (on && !c->ev_pool) {
+        c->ev_pool = new (std::nothrow) std::vector<hipEvent_t>();
+        c->ev_kind = new (std::nothrow) std::vector<int>();
+        if (!c->ev_pool || !c->ev_kind) return DG_ENOMEM;
+    }
+    c->timing = on ? 1 : 0;
+    return DG_OK;
+}
+
+dg_status dg_timing_read(dg_ctx *c, double *face_ms, long long *face_n, double *vol_ms, long long *vol_n,
+                         double *cfl_ms, long long *cfl_n, long long *dropped)
+{
+    if (!c) return DG_EINVAL;
+    double ms[3] = {0, 0, 0};
+    long long n[3] = {0, 0, 0};
+    if (c->ev_used > 0) {
+        if (!ok(hipEventSynchronize((*c->ev_pool)[2 * c->ev_used - 1]))) return DG_EDEVICE;
+        for (long long i = 0; i < c->ev_used; ++i) {
+            float t = 0.0f;
+            if (!ok(hipEventElapsedTime(&t, (*c->ev_pool)[2 * i], (*c->ev_pool)[2 * i + 1]))) return DG_EDEVICE;
+            const int k = (*c->ev_kind)[i];
+            ms[k] += t;
+            ++n[k];
+        }
+    }
+    if (face_ms) *face_ms = ms[0];
+    if (face_n) *face_n = n[0];
+    if (vol_ms) *vol_ms = ms[1];
+    if (vol_n) *vol_n = n[1];
+    if (cfl_ms) *cfl_ms = ms[2];
+    if (cfl_n) *cfl_n = n[2];
+    if (dropped) *dropped = c->ev_dropped;
+    c->ev_used = 0;
+    c->ev_dropped = 0;
+    if (c->ev_kind) c->ev_kind->clear();
+    return DG_OK;
 }
 
 size_t dg_state_len(const dg_ctx *c) { return c ? (size_t)c->ncells * c->F * c->NP : 0; }
