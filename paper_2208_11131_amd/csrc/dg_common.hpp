@@ -78,8 +78,22 @@ struct FaceArgs {
 
 struct CflArgs {
     const double *w;
-    unsigned long long *maxbits;   // [0] = c_s max, [1] = |v| max (bit patterns)
+    double *part;          // [block][2]: c_s max, |v| max of each block
     int cells_per_block;
 };
+
+// Number of face blocks (grid.x) for pencils of C faces: the largest over the
+// directions of ceil(nf[a] / C) times the extents of the other axes.
+inline long long face_pencils(const Geo &g, int dim, int C)
+{
+    long long mx = 0;
+    for (int a = 0; a < dim; ++a) {
+        long long n = (g.nf[a] + C - 1) / C;
+        for (int b = 0; b < 3; ++b)
+            if (b != a) n *= g.n[b];
+        if (n > mx) mx = n;
+    }
+    return mx;
+}
 
 }  // namespace dgk

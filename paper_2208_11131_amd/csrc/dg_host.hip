@@ -206,18 +206,35 @@ dg_status ensure_tables(int dev)
 // small kernels
 // ---------------------------------------------------------------------------
 
-__global__ void cfl_finalize(unsigned long long *bits, double *res, double *dt_copy, double num)
+__device__ __forceinline__ double nanmax2(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// Reduce the per-block maxima of the CFL kernel (one block of 256 threads,
+// fixed order) and form dt = f_CFL h / (2 p (c_max + v_max)).
+__global__ void cfl_finalize(const double *part, int nblk, double *res, double *dt_copy, double num)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const double cm = __longlong_as_double((long long)bits[0]);
-        const double vm = __longlong_as_double((long long)bits[1]);
-        const double dt = num / (cm + vm);
+    __shared__ double rc[256], rv[256];
+    const int t = threadIdx.x;
+    double c = 0.0, v = 0.0;
+    for (int b = t; b < nblk; b += blockDim.x) {
+        c = nanmax2(c, part[2 * b]);
+        v = nanmax2(v, part[2 * b + 1]);
+    }
+    rc[t] = c;
+    rv[t] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+            rc[t] = nanmax2(rc[t], rc[t + s]);
+            rv[t] = nanmax2(rv[t], rv[t + s]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double dt = num / (rc[0] + rv[0]);
         res[0] = dt;
-        res[1] = cm;
-        res[2] = vm;
+        res[1] = rc[0];
+        res[2] = rv[0];
         if (dt_copy) dt_copy[0] = dt;
-        bits[0] = 0ULL;
-        bits[1] = 0ULL;
     }
 }
 
@@ -289,8 +306,9 @@ struct dg_ctx {
     double cfl;
     int device;
     bool grad;
+    int phys;    // 0 Euler, 1 Navier-Stokes, 2 artificial viscosity
     KernelSet ks, ks64;
-    int vol_C, vol_T, face_C, face_T, cfl_C, cfl_T;
+    int vol_C, vol_T, face_C, face_T, cfl_C, cfl_T, cfl_blocks;
     size_t vol_lds, vol_lds_forced, face_lds, cfl_lds;
     int stages;
     double *reg[3];
@@ -298,7 +316,7 @@ struct dg_ctx {
     size_t fb_bytes;
     double *R[2];
     int rpar;
-    unsigned long long *maxbits;   // [2]
+    double *cfl_part;              // [cfl_blocks][2]
     double *scal;                  // [0] dt, [1] cmax, [2] vmax, [3..] totals
     int *flag;
     double *tot_part;
@@ -322,18 +340,18 @@ void free_bufs(dg_ctx *c)
     if (c->fb) (void)hipFree(c->fb);
     for (int i = 0; i < 2; ++i)
         if (c->R[i]) (void)hipFree(c->R[i]);
-    if (c->maxbits) (void)hipFree(c->maxbits);
+    if (c->cfl_part) (void)hipFree(c->cfl_part);
     if (c->scal) (void)hipFree(c->scal);
     if (c->flag) (void)hipFree(c->flag);
     if (c->tot_part) (void)hipFree(c->tot_part);
 }
 
-void get_kernels(int dim, int prec, int P, bool grad, KernelSet *k)
+void get_kernels(int dim, int prec, int P, int phys, KernelSet *k)
 {
     if (dim == 2)
-        (prec == DG_PREC_FP64 ? dgk::dgk_get_2d_f64 : dgk::dgk_get_2d_f32)(P, grad, k);
+        (prec == DG_PREC_FP64 ? dgk::dgk_get_2d_f64 : dgk::dgk_get_2d_f32)(P, phys, k);
     else
-        (prec == DG_PREC_FP64 ? dgk::dgk_get_3d_f64 : dgk::dgk_get_3d_f32)(P, grad, k);
+        (prec == DG_PREC_FP64 ? dgk::dgk_get_3d_f64 : dgk::dgk_get_3d_f32)(P, phys, k);
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
@@ -375,11 +393,8 @@ dg_status stage(dg_ctx *c, dgk::VolArgs va, hipStream_t s)
     fa.w = va.cur;
     fa.fb = c->fb;
     fa.faces_per_block = c->face_C;
-    long long maxf = 0;
-    for (int a = 0; a < c->dim; ++a)
-        if (c->geo.nfaces[a] > maxf) maxf = c->geo.nfaces[a];
     void *fargs[] = {&c->ph, &c->geo, &fa};
-    dim3 fg((unsigned)((maxf + c->face_C - 1) / c->face_C), (unsigned)c->dim);
+    dim3 fg((unsigned)dgk::face_pencils(c->geo, c->dim, c->face_C), (unsigned)c->dim);
     dg_status st = launch(c, 0, c->ks.face, fg, dim3(c->face_T), fargs, c->face_lds, s);
     if (st != DG_OK) return st;
     va.fb = c->fb;
@@ -402,14 +417,14 @@ dg_status run_cfl(dg_ctx *c, const double *w, double *dt_copy, hipStream_t s)
 {
     dgk::CflArgs ca;
     ca.w = w;
-    ca.maxbits = c->maxbits;
+    ca.part = c->cfl_part;
     ca.cells_per_block = c->cfl_C;
     void *args[] = {&c->ph, &c->geo, &ca};
-    dim3 g((unsigned)((c->ncells + c->cfl_C - 1) / c->cfl_C));
+    dim3 g((unsigned)c->cfl_blocks);
     dg_status st = launch(c, 2, c->ks64.cfl, g, dim3(c->cfl_T), args, c->cfl_lds, s);
     if (st != DG_OK) return st;
     const double num = c->cfl * c->ph.h / (2.0 * c->P);
-    hipLaunchKernelGGL(cfl_finalize, dim3(1), dim3(64), 0, s, c->maxbits, c->scal, dt_copy, num);
+    hipLaunchKernelGGL(cfl_finalize, dim3(1), dim3(256), 0, s, c->cfl_part, c->cfl_blocks, c->scal, dt_copy, num);
     return ok(hipGetLastError()) ? DG_OK : DG_EDEVICE;
 }
 
@@ -616,8 +631,9 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         ph.eps_fac = h / order;
     }
     c->grad = ph.ns_on || ph.av_on;
-    get_kernels(d, c->precision, order, c->grad, &c->ks);
-    get_kernels(d, DG_PREC_FP64, order, c->grad, &c->ks64);
+    c->phys = ph.av_on ? 2 : (ph.ns_on ? 1 : 0);
+    get_kernels(d, c->precision, order, c->phys, &c->ks);
+    get_kernels(d, DG_PREC_FP64, order, c->phys, &c->ks64);
     if (!c->ks.vol || !c->ks.face || !c->ks64.cfl) {
         delete c;
         return DG_EUNSUPPORTED;
@@ -629,10 +645,10 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         c->vol_C = o.cells_per_block;
     else
         c->vol_C = std::max(1, 256 / c->NP);
-    while (c->vol_C > 1 && c->ks.vol_lds(c->vol_C, c->F, Fx) > LDS_MAX) --c->vol_C;
+    while (c->vol_C > 1 && c->ks.vol_lds(c->vol_C, Fx) > LDS_MAX) --c->vol_C;
     c->vol_T = std::min(512, std::max(64, roundup(c->vol_C * c->NP, 64)));
-    c->vol_lds = c->ks.vol_lds(c->vol_C, c->F, c->F);
-    c->vol_lds_forced = c->ks.vol_lds(c->vol_C, c->F, Fx);
+    c->vol_lds = c->ks.vol_lds(c->vol_C, c->F);
+    c->vol_lds_forced = c->ks.vol_lds(c->vol_C, Fx);
     if (c->vol_lds > LDS_MAX) {
         delete c;
         return DG_EUNSUPPORTED;
@@ -641,13 +657,14 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         c->face_C = o.faces_per_block;
     else
         c->face_C = std::max(1, 128 / c->K);
-    while (c->face_C > 1 && c->ks.face_lds(c->face_C, c->F) > 64 * 1024) --c->face_C;
+    while (c->face_C > 1 && c->ks.face_lds(c->face_C) > 64 * 1024) --c->face_C;
     c->face_T = std::min(512, std::max(64, roundup(c->face_C * c->K, 64)));
-    c->face_lds = c->ks.face_lds(c->face_C, c->F);
+    c->face_lds = c->ks.face_lds(c->face_C);
     c->cfl_C = std::max(1, 256 / c->NP);
     c->cfl_T = 256;
     while (c->cfl_C > 1 && c->ks64.cfl_lds(c->cfl_C, c->cfl_T) > 64 * 1024) --c->cfl_C;
     c->cfl_lds = c->ks64.cfl_lds(c->cfl_C, c->cfl_T);
+    c->cfl_blocks = (int)((c->ncells + c->cfl_C - 1) / c->cfl_C);
     if (c->face_lds > LDS_MAX || c->cfl_lds > LDS_MAX) {
         delete c;
         return DG_EUNSUPPORTED;
@@ -668,8 +685,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
             good = ok(hipMalloc(&c->R[i], c->ncells * sizeof(double)));
             good = good && ok(hipMemset(c->R[i], 0, c->ncells * sizeof(double)));
         }
-    good = good && ok(hipMalloc(&c->maxbits, 2 * sizeof(unsigned long long)));
-    good = good && ok(hipMemset(c->maxbits, 0, 2 * sizeof(unsigned long long)));
+    good = good && ok(hipMalloc(&c->cfl_part, (size_t)c->cfl_blocks * 2 * sizeof(double)));
     good = good && ok(hipMalloc(&c->scal, 16 * sizeof(double)));
     good = good && ok(hipMalloc(&c->flag, sizeof(int)));
     good = good && ok(hipMemset(c->flag, 0, sizeof(int)));

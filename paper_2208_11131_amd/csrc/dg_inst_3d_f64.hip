@@ -1,42 +1,45 @@
-// Kernel instantiations: dim = 3, bulk precision double, orders 1..8.
+// Kernel instantiations: dim = 3, bulk precision double, orders 1..8,
+// physics variants Euler / Navier-Stokes / artificial viscosity.
 #include "dg_kernels.hpp"
 #include "dg_registry.hpp"
 
 namespace dgk {
 
 namespace {
-template <int P, bool G>
+template <int P, int PH>
 void fill(KernelSet *k)
 {
-    k->vol = (const void *)&vol_kernel<3, P, double, G>;
-    k->face = (const void *)&face_kernel<3, P, double, G>;
-    k->vol_lds = &vol_lds_bytes<3, P, double>;
-    k->face_lds = &face_lds_bytes<3, P, double, G>;
-    k->cfl = (const void *)&cfl_kernel<3, P>;
+    k->vol = (const void *)&vol_kernel<3, P, double, PH>;
+    k->face = (const void *)&face_kernel<3, P, double, PH>;
+    k->vol_lds = &vol_lds_bytes<3, P, double, PH>;
+    k->face_lds = &face_lds_bytes<3, P, double, PH>;
+    k->cfl = (const void *)&cfl_kernel<3, P, PH>;
     k->cfl_lds = &cfl_lds_bytes<3, P>;
 }
 
 template <int P>
-void pick(bool grad, KernelSet *k)
+void pick(int ph, KernelSet *k)
 {
-    if (grad)
-        fill<P, true>(k);
+    if (ph == 0)
+        fill<P, 0>(k);
+    else if (ph == 1)
+        fill<P, 1>(k);
     else
-        fill<P, false>(k);
+        fill<P, 2>(k);
 }
 }  // namespace
 
-void dgk_get_3d_f64(int P, bool grad, KernelSet *k)
+void dgk_get_3d_f64(int P, int ph, KernelSet *k)
 {
     switch (P) {
-    case 1: pick<1>(grad, k); break;
-    case 2: pick<2>(grad, k); break;
-    case 3: pick<3>(grad, k); break;
-    case 4: pick<4>(grad, k); break;
-    case 5: pick<5>(grad, k); break;
-    case 6: pick<6>(grad, k); break;
-    case 7: pick<7>(grad, k); break;
-    case 8: pick<8>(grad, k); break;
+    case 1: pick<1>(ph, k); break;
+    case 2: pick<2>(ph, k); break;
+    case 3: pick<3>(ph, k); break;
+    case 4: pick<4>(ph, k); break;
+    case 5: pick<5>(ph, k); break;
+    case 6: pick<6>(ph, k); break;
+    case 7: pick<7>(ph, k); break;
+    case 8: pick<8>(ph, k); break;
     default: *k = KernelSet{};
     }
 }

@@ -53,22 +53,22 @@ __device__ __forceinline__ T mat(int k, int i)
     return t.Bd[k][i];                       // derivative of mode k at point i
 }
 
-// Apply a p x p operator along axis AX of ncell*nper arrays of p^DA entries.
+// Apply a p x p operator along axis AX of ncell*NPER arrays of p^DA entries.
 // Array (c, f) starts at in + c*in_cs + f*p^DA (likewise out).  Each work item
 // is one line along AX: p loads, p*p FMAs with table operands, p stores.
-template <int P, int DA, int AX, typename T, int MAT, bool ACC>
+template <int P, int DA, int AX, typename T, int MAT, bool ACC, int NPER>
 __device__ __forceinline__ void axis_pass(const T *__restrict__ in, int in_cs, T *__restrict__ out, int out_cs,
-                                          int ncell, int nper)
+                                          int ncell)
 {
     constexpr int NA = ipow(P, DA);
     constexpr int NL = NA / P;
     constexpr int S = ipow(P, AX);
-    const int nitems = ncell * nper * NL;
+    const int nitems = ncell * NPER * NL;
     for (int q = threadIdx.x; q < nitems; q += blockDim.x) {
         const int cf = q / NL;
         const int t = q - cf * NL;
-        const int c = cf / nper;
-        const int f = cf - c * nper;
+        const int c = cf / NPER;
+        const int f = cf - c * NPER;
         const int lo = t % S, hi = t / S;
         const int off = f * NA + lo + hi * S * P;
         const T *pi = in + c * in_cs + off;
@@ -84,6 +84,25 @@ __device__ __forceinline__ void axis_pass(const T *__restrict__ in, int in_cs, T
             po[i * S] = acc;
         }
     }
+}
+
+// Fields per physics variant: PH = 0 Euler, 1 Navier-Stokes, 2 artificial
+// viscosity (alpha field; Navier-Stokes terms switched at run time).
+template <int D, int PH>
+struct Fld {
+    static constexpr int Fc = D + 2;
+    static constexpr int F = D + 2 + (PH == 2 ? 1 : 0);
+    static constexpr bool GRAD = PH > 0;
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
+// map them so that each XCD works on one contiguous range of logical blocks
+// (neighbouring tiles then share that XCD's L2).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    const unsigned q = nb / 8, r = nb % 8;
+    const unsigned x = b % 8, k = b / 8;
+    return x * q + (x < r ? x : r) + k;
 }
 
 // ---------------------------------------------------------------------------
@@ -196,95 +215,91 @@ __device__ __forceinline__ T clamp_alpha(T al, T amax)
 // ---------------------------------------------------------------------------
 // face kernel
 // ---------------------------------------------------------------------------
+//
+// One block computes a pencil of C consecutive faces of direction AX (fixed
+// transverse coordinates).  It loads the C + 1 cells that these faces
+// separate once, so every cell is read about once per direction.
 
-// Cell index of the lower (side 0) or upper (side 1) cell of face fi of
-// direction ax, and whether it is a mirrored ghost.
-__device__ __forceinline__ long long face_cell(const Geo &g, int ax, long long fi, int side, bool &mirror)
-{
-    int co[3] = {0, 0, 0};
-    long long r = fi;
-    for (int b = 0; b < 3; ++b) {
-        const int nb = (b == ax) ? g.nf[b] : g.n[b];
-        co[b] = (int)(r % nb);
-        r /= nb;
-    }
-    mirror = false;
-    int ia = co[ax] - (side == 0 ? 1 : 0);
-    if (g.bc[ax] == 0) {
-        if (ia < 0) ia += g.n[ax];
-    } else {
-        if (ia < 0) {
-            ia = 0;
-            mirror = true;
-        } else if (ia >= g.n[ax]) {
-            ia = g.n[ax] - 1;
-            mirror = true;
-        }
-    }
-    co[ax] = ia;
-    return co[0] + (long long)g.n[0] * (co[1] + (long long)g.n[1] * co[2]);
-}
-
-template <int D, int P, int AX, typename T, bool GRAD>
-__device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const FaceArgs &a, unsigned char *smem)
+template <int D, int P, int AX, typename T, int PH>
+__device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const FaceArgs &a, unsigned char *smem,
+                                          long long pen_id)
 {
     constexpr int NP = ipow(P, D);
     constexpr int K = NP / P;          // face points (and transverse modes)
-    const int Fc = D + 2;
-    const int F = Fc + ph.av_on;
+    constexpr int Fc = Fld<D, PH>::Fc;
+    constexpr int F = Fld<D, PH>::F;
+    constexpr bool GRAD = Fld<D, PH>::GRAD;
+    constexpr int FNP = F * NP;
+    constexpr int NA = GRAD ? 4 : 2;
+    constexpr int S = ipow(P, AX);
     const int C = a.faces_per_block;
-    const long long nfc = geo.nfaces[AX];
-    const long long f0 = (long long)blockIdx.x * C;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int Q = C * F * K;
-    const int NA = GRAD ? 4 : 2;
+    const int na = geo.n[AX], nfa = geo.nf[AX];
+    const int npl = (nfa + C - 1) / C;
+    const long long line = pen_id / npl;
+    const int a0 = (int)(pen_id - line * npl) * C;
+    const int nface = min(C, nfa - a0);
+    int co[3] = {0, 0, 0};
+    {
+        long long r = line;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            if (b != AX) {
+                co[b] = (int)(r % geo.n[b]);
+                r /= geo.n[b];
+            }
+    }
 
-    long long *cellidx = (long long *)smem;               // [2][C]
-    int *mir = (int *)(cellidx + 2 * C);                  // [2][C]
-    T *base = (T *)(smem + ((2 * C * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16);
-    T *WL = base;                                         // [C][F][NP]
-    T *WR = WL + C * F * NP;
-    T *A = WR + C * F * NP;                               // [NA][C][F][K]
-    T *Sx = (P >= 3) ? WL : (A + NA * Q);                 // scratch [6][C][F][K]
+    long long *cellidx = (long long *)smem;               // [C+1]
+    int *mir = (int *)(cellidx + (C + 1));                // [C+1]
+    T *W = (T *)(smem + (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16);   // [C+1][F][NP]
+    T *A = W + (C + 1) * FNP;                             // [NA][C][F][K]
+    T *Sx = ((C + 1) * FNP >= 5 * Q) ? W : (A + NA * Q);  // scratch [5][C][F][K]
 
-    for (int e = tid; e < 2 * C; e += nt) {
-        const int side = e / C, c = e - side * C;
-        long long fi = f0 + c;
-        if (fi >= nfc) fi = nfc - 1;
-        bool m;
-        cellidx[e] = face_cell(geo, AX, fi, side, m);
-        mir[e] = m ? 1 : 0;
+    for (int s = tid; s <= C; s += nt) {
+        int ca = a0 + s - 1;
+        int m = 0;
+        if (geo.bc[AX] == 0) {
+            ca = ((ca % na) + na) % na;   // pencils may be longer than the axis
+        } else {
+            if (ca < 0) {
+                ca = 0;
+                m = 1;
+            } else if (ca >= na) {
+                ca = na - 1;
+                m = 1;
+            }
+        }
+        int cc[3] = {co[0], co[1], co[2]};
+        cc[AX] = ca;
+        cellidx[s] = cc[0] + (long long)geo.n[0] * (cc[1] + (long long)geo.n[1] * cc[2]);
+        mir[s] = m;
     }
     __syncthreads();
-    for (int i = tid; i < 2 * C * F * NP; i += nt) {
-        const int side = i / (C * F * NP);
-        const int r = i - side * C * F * NP;
-        const int c = r / (F * NP);
-        const int e = r - c * F * NP;
-        double v = a.w[cellidx[side * C + c] * (long long)(F * NP) + e];
-        if (mir[side * C + c]) {
-            const int m = e % NP;
-            const int la = (m / ipow(P, AX)) % P;
-            if (la & 1) v = -v;
-        }
-        (side ? WR : WL)[r] = (T)v;
+    for (int i = tid; i < (C + 1) * FNP; i += nt) {
+        const int s = i / FNP, e = i - s * FNP;
+        double v = a.w[cellidx[s] * FNP + e];
+        if (mir[s] && (((e % NP) / S) % P) & 1) v = -v;
+        W[i] = (T)v;
     }
     __syncthreads();
 
     // normal contraction: traces (and recovery partial sums) per transverse mode
     {
-        constexpr int S = ipow(P, AX);
         const Tab<T> &tb = TabSel<T>::get(P);
         for (int q = tid; q < C * F * K; q += nt) {
             const int cf = q / K;
             const int t = q - cf * K;
+            const int c = cf / F, f = cf - c * F;
             const int lo = t % S, hi = t / S;
-            const int off = cf * NP + lo + hi * S * P;
+            const int offL = c * FNP + f * NP + lo + hi * S * P;
+            const int offR = offL + FNP;
             T xl[P], xr[P];
 #pragma unroll
             for (int m = 0; m < P; ++m) {
-                xl[m] = WL[off + m * S];
-                xr[m] = WR[off + m * S];
+                xl[m] = W[offL + m * S];
+                xr[m] = W[offR + m * S];
             }
             T tl = T(0), tr = T(0);
 #pragma unroll
@@ -313,8 +328,8 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     // transverse transforms to the face Gauss points
     const T *tLp, *tRp, *utp = nullptr, *rnp = nullptr, *d1p = nullptr, *d2p = nullptr;
     if (D == 2) {
-        axis_pass<P, 1, 0, T, M_B, false>(A, K, Sx, K, NA * C * F, 1);
-        if (GRAD) axis_pass<P, 1, 0, T, M_BD, false>(A + 2 * Q, K, Sx + 4 * Q, K, C * F, 1);
+        axis_pass<P, 1, 0, T, M_B, false, 1>(A, K, Sx, K, NA * C * F);
+        if (GRAD) axis_pass<P, 1, 0, T, M_BD, false, 1>(A + 2 * Q, K, Sx + 4 * Q, K, C * F);
         __syncthreads();
         tLp = Sx;
         tRp = Sx + Q;
@@ -322,22 +337,23 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         rnp = Sx + 3 * Q;
         d1p = Sx + 4 * Q;
     } else {
-        axis_pass<P, 2, 0, T, M_B, false>(A, K, Sx, K, NA * C * F, 1);
-        if (GRAD) axis_pass<P, 2, 0, T, M_BD, false>(A + 2 * Q, K, Sx + 4 * Q, K, C * F, 1);
+        // (t1, t2) = transverse axes of the face in ascending order
+        axis_pass<P, 2, 0, T, M_B, false, 1>(A, K, Sx, K, NA * C * F);
+        if (GRAD) axis_pass<P, 2, 0, T, M_BD, false, 1>(A + 2 * Q, K, Sx + 4 * Q, K, C * F);
         __syncthreads();
-        axis_pass<P, 2, 1, T, M_B, false>(Sx, K, A, K, NA * C * F, 1);
-        if (GRAD) axis_pass<P, 2, 1, T, M_BD, false>(Sx + 2 * Q, K, Sx + 5 * Q, K, C * F, 1);
+        axis_pass<P, 2, 1, T, M_B, false, 1>(Sx, K, A, K, NA * C * F);
         __syncthreads();
         if (GRAD) {
-            axis_pass<P, 2, 1, T, M_B, false>(Sx + 4 * Q, K, Sx, K, C * F, 1);
+            axis_pass<P, 2, 1, T, M_BD, false, 1>(Sx + 2 * Q, K, Sx, K, C * F);
+            axis_pass<P, 2, 1, T, M_B, false, 1>(Sx + 4 * Q, K, Sx + Q, K, C * F);
             __syncthreads();
         }
         tLp = A;
         tRp = A + Q;
         utp = A + 2 * Q;
         rnp = A + 3 * Q;
-        d1p = Sx;
-        d2p = Sx + 5 * Q;
+        d2p = Sx;
+        d1p = Sx + Q;
     }
 
     // point fluxes
@@ -346,8 +362,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     T *fb = (T *)a.fb + geo.fb_off[AX];
     for (int q = tid; q < C * K; q += nt) {
         const int c = q / K, k = q - c * K;
-        const long long fi = f0 + c;
-        if (fi >= nfc) continue;
+        if (c >= nface) continue;
         T uL[D + 2], uR[D + 2], Fh[D + 2];
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) {
@@ -361,23 +376,21 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
             constexpr int T1 = (AX == 0) ? 1 : 0;             // transverse axes, ascending
             constexpr int T2 = (D == 3) ? ((AX == 2) ? 1 : 2) : 0;
 #pragma unroll
-            for (int f = 0; f < D + 3; ++f) {
-                if (f < F) {
-                    const int idx = (c * F + f) * K + k;
-                    ut[f] = utp[idx];
-                    g[AX][f] = rnp[idx] * (T)ph.inv_fh;
-                    g[T1][f] = d1p[idx] * (T)ph.two_over_h;
-                    if (D == 3) g[T2][f] = d2p[idx] * (T)ph.two_over_h;
-                }
+            for (int f = 0; f < F; ++f) {
+                const int idx = (c * F + f) * K + k;
+                ut[f] = utp[idx];
+                g[AX][f] = rnp[idx] * (T)ph.inv_fh;
+                g[T1][f] = d1p[idx] * (T)ph.two_over_h;
+                if (D == 3) g[T2][f] = d2p[idx] * (T)ph.two_over_h;
             }
             const Prim<D, T> s = primitives<D, T>(ut, gamma);
-            if (ph.ns_on) {
+            if (PH == 1 || ph.ns_on) {
                 T fv[D + 2];
                 ns_flux<D, T>(ut, s, g, AX, gamma, (T)ph.nu, (T)ph.kappa, fv);
 #pragma unroll
                 for (int f = 0; f < D + 2; ++f) Fh[f] -= fv[f];
             }
-            if (ph.av_on) {
+            if (PH == 2) {
                 const T cs = sqrt(gamma * s.p * s.ir);
                 const T eps = (T)ph.av_scale * clamp_alpha(ut[D + 2], (T)ph.alpha_max) * cs * (T)ph.eps_fac;
 #pragma unroll
@@ -386,40 +399,53 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         }
         T gk = tb.g[k % P];
         if (D == 3) gk *= tb.g[k / P];
+        int cf[3] = {co[0], co[1], co[2]};
+        cf[AX] = a0 + c;
+        const long long nd0 = (AX == 0) ? nfa : geo.n[0];
+        const long long nd1 = (AX == 1) ? nfa : geo.n[1];
+        const long long fi = cf[0] + nd0 * (cf[1] + nd1 * cf[2]);
         T *dst = fb + fi * (long long)(Fc * K) + k;
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) dst[f * K] = gk * Fh[f];
     }
 }
 
-template <int D, int P, typename T, bool GRAD>
+template <int D, int P, typename T, int PH>
 __global__ void __launch_bounds__(512) face_kernel(Phys ph, Geo geo, FaceArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int ax = blockIdx.y;
-    if ((long long)blockIdx.x * a.faces_per_block >= geo.nfaces[ax]) return;
+    const int C = a.faces_per_block;
+    // pencils of direction ax: ceil(nf/C) per line, lines = product of the other extents
+    long long npen = (geo.nf[ax] + C - 1) / C;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        if (b != ax) npen *= geo.n[b];
+    const unsigned bid = xcd_block(blockIdx.x, gridDim.x);
+    if ((long long)bid >= npen) return;
     if (ax == 0)
-        face_body<D, P, 0, T, GRAD>(ph, geo, a, smem);
+        face_body<D, P, 0, T, PH>(ph, geo, a, smem, bid);
     else if (ax == 1)
-        face_body<D, P, 1, T, GRAD>(ph, geo, a, smem);
+        face_body<D, P, 1, T, PH>(ph, geo, a, smem, bid);
     else if (D == 3)
-        face_body<D, P, (D == 3 ? 2 : 0), T, GRAD>(ph, geo, a, smem);
+        face_body<D, P, (D == 3 ? 2 : 0), T, PH>(ph, geo, a, smem, bid);
 }
 
-// LDS bytes of the face kernel for C faces per block: header, the two cells'
-// coefficients W (2 C F p^d), the contraction results A (NA C F p^(d-1)) and
-// a scratch of 6 C F p^(d-1) that overlays W when p >= 3 (W is dead after
-// the normal contraction).
-template <int D, int P, typename T, bool GRAD>
-size_t face_lds_bytes(int C, int F)
+// LDS bytes of the face kernel for pencils of C faces: slot indices, the C+1
+// cells' coefficients W, the contraction results A (NA C F p^(d-1)) and a
+// scratch of 5 C F p^(d-1) that overlays W when W is large enough (W is dead
+// after the normal contraction).
+template <int D, int P, typename T, int PH>
+size_t face_lds_bytes(int C)
 {
     constexpr int NP = ipow(P, D);
     constexpr int K = NP / P;
-    const size_t hdr = ((2 * C * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16;
+    constexpr int F = Fld<D, PH>::F;
+    const size_t hdr = (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16;
     const size_t Q = (size_t)C * F * K;
-    const size_t W = 2 * (size_t)C * F * NP;
-    const size_t NA = GRAD ? 4 : 2;
-    const size_t tot = W + NA * Q + (P >= 3 ? 0 : 6 * Q);
+    const size_t W = (size_t)(C + 1) * F * NP;
+    const size_t NA = Fld<D, PH>::GRAD ? 4 : 2;
+    const size_t tot = W + NA * Q + (W >= 5 * Q ? 0 : 5 * Q);
     return hdr + sizeof(T) * tot;
 }
 
@@ -427,87 +453,130 @@ size_t face_lds_bytes(int C, int F)
 // volume kernel
 // ---------------------------------------------------------------------------
 
-template <int D, int P, typename T, bool GRAD>
+template <int D, int P, typename T, int PH>
 __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
 {
     constexpr int NP = ipow(P, D);
     constexpr int K = NP / P;
+    constexpr int Fc = Fld<D, PH>::Fc;
+    constexpr int F = Fld<D, PH>::F;
+    constexpr bool GRAD = Fld<D, PH>::GRAD;
+    constexpr int FNP = F * NP;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Fc = D + 2;
-    const int F = Fc + ph.av_on;
-    const int Fx = F + (a.forcing ? D : 0);
+    const bool forced = a.forcing != nullptr;
+    const int Fx = F + (forced ? D : 0);
     const int C = a.cells_per_block;
     const int tid = threadIdx.x, nt = blockDim.x;
     const long long NC = geo.ncells;
-    const long long c0 = (long long)blockIdx.x * C;
+    const long long c0 = (long long)xcd_block(blockIdx.x, gridDim.x) * C;
     const int cs_x = Fx * NP;                 // per-cell stride of X0/X1
-    const int cs_g = D * F * NP;              // per-cell stride of G
+    constexpr int cs_g = D * F * NP;          // per-cell stride of G
 
-    double *cellv = (double *)smem;           // [C][2]: wiggle source, new mean checks
-    int *blkflag = (int *)(cellv + 2 * C);
-    T *X0 = (T *)(smem + ((2 * C * sizeof(double) + sizeof(int) + 15) / 16) * 16);
+    long long *fidx = (long long *)smem;      // [C][D][2] lower/upper face index per axis
+    double *cellv = (double *)(fidx + 2 * D * C);   // [C]: wiggle source
+    int *blkflag = (int *)(cellv + C);
+    T *X0 = (T *)(smem + ((C * (2 * D * sizeof(long long) + sizeof(double)) + sizeof(int) + 15) / 16) * 16);
     T *X1 = X0 + C * cs_x;
     T *G = X1 + C * cs_x;
     const Tab<T> &tb = TabSel<T>::get(P);
 
-    // 1. load the tile's weights (and forcing coefficients)
-    const long long gbase = c0 * F * NP, gend = NC * F * NP;
-    for (int i = tid; i < C * F * NP; i += nt) {
-        const int c = i / (F * NP), r = i - c * (F * NP);
+    // 1. load the tile's weights (and forcing coefficients); per-cell data
+    const long long gbase = c0 * FNP, gend = NC * FNP;
+    for (int i = tid; i < C * FNP; i += nt) {
+        const int c = i / FNP, r = i - c * FNP;
         long long gi = gbase + i;
-        if (gi >= gend) gi = (NC - 1) * F * NP + r;
+        if (gi >= gend) gi = (NC - 1) * FNP + r;
         X0[c * cs_x + r] = (T)a.cur[gi];
     }
-    if (a.forcing) {
+    if (forced) {
         for (int i = tid; i < C * D * NP; i += nt) {
             const int c = i / (D * NP), r = i - c * (D * NP);
             long long cc = c0 + c;
             if (cc >= NC) cc = NC - 1;
-            X0[c * cs_x + F * NP + r] = (T)a.forcing[cc * D * NP + r];
+            X0[c * cs_x + FNP + r] = (T)a.forcing[cc * D * NP + r];
         }
     }
     if (tid == 0) *blkflag = 0;
-    for (int cl = tid; ph.av_on && cl < C; cl += nt) {
-        // sensor S of the current state and the wiggle source (Sec. 4.1)
+    for (int cl = tid; cl < C; cl += nt) {
         long long cc = c0 + cl;
         if (cc >= NC) cc = NC - 1;
-        const double *wr = a.cur + cc * F * NP;
-        double all = 0.0, top = 0.0;
-        for (int m = 0; m < NP; ++m) {
-            const double x = wr[m];
-            all += x * x;
-            bool t = false;
-            int r = m;
+        int co[3];
+        long long t = cc;
 #pragma unroll
-            for (int b = 0; b < D; ++b) {
-                t = t || (r % P == P - 1);
-                r /= P;
-            }
-            if (t) top += x * x;
+        for (int b = 0; b < 3; ++b) {
+            co[b] = (int)(t % geo.n[b]);
+            t /= geo.n[b];
         }
-        const double S = all > 0.0 ? top / all : 0.0;
-        const double Rp = a.R_prev ? a.R_prev[cc] : 0.0;
-        cellv[2 * cl] = (S > ph.s_thr) ? ph.f_w * fmax(0.0, Rp) : 0.0;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            const int nfa = geo.nf[ax];
+            long long flo = 0, fhi = 0, mul = 1;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const int nb = (b == ax) ? nfa : geo.n[b];
+                int ilo = co[b], ihi = co[b];
+                if (b == ax) {
+                    ihi = co[b] + 1;
+                    if (ihi >= nfa) ihi -= nfa;   // periodic wrap (outflow has nf = n + 1)
+                }
+                flo += ilo * mul;
+                fhi += ihi * mul;
+                mul *= nb;
+            }
+            fidx[(cl * D + ax) * 2] = flo;
+            fidx[(cl * D + ax) * 2 + 1] = fhi;
+        }
+        if (PH == 2) {
+            // sensor S of the current state and the wiggle source (Sec. 4.1)
+            const double *wr = a.cur + cc * FNP;
+            double all = 0.0, top = 0.0;
+            for (int m = 0; m < NP; ++m) {
+                const double x = wr[m];
+                all += x * x;
+                bool tp = false;
+                int r = m;
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    tp = tp || (r % P == P - 1);
+                    r /= P;
+                }
+                if (tp) top += x * x;
+            }
+            const double Sv = all > 0.0 ? top / all : 0.0;
+            const double Rp = a.R_prev ? a.R_prev[cc] : 0.0;
+            cellv[cl] = (Sv > ph.s_thr) ? ph.f_w * fmax(0.0, Rp) : 0.0;
+        }
     }
     __syncthreads();
 
     // 2. point values of all fields: one operator pass per axis
-    axis_pass<P, D, 0, T, M_B, false>(X0, cs_x, X1, cs_x, C, Fx);
-    __syncthreads();
-    axis_pass<P, D, 1, T, M_B, false>(X1, cs_x, X0, cs_x, C, Fx);
-    __syncthreads();
-    if (D == 3) {
-        axis_pass<P, D, (D == 3 ? 2 : 0), T, M_B, false>(X0, cs_x, X1, cs_x, C, Fx);
+    if (forced) {
+        axis_pass<P, D, 0, T, M_B, false, F + D>(X0, cs_x, X1, cs_x, C);
         __syncthreads();
+        axis_pass<P, D, 1, T, M_B, false, F + D>(X1, cs_x, X0, cs_x, C);
+        __syncthreads();
+        if (D == 3) {
+            axis_pass<P, D, (D == 3 ? 2 : 0), T, M_B, false, F + D>(X0, cs_x, X1, cs_x, C);
+            __syncthreads();
+        }
+    } else {
+        axis_pass<P, D, 0, T, M_B, false, F>(X0, cs_x, X1, cs_x, C);
+        __syncthreads();
+        axis_pass<P, D, 1, T, M_B, false, F>(X1, cs_x, X0, cs_x, C);
+        __syncthreads();
+        if (D == 3) {
+            axis_pass<P, D, (D == 3 ? 2 : 0), T, M_B, false, F>(X0, cs_x, X1, cs_x, C);
+            __syncthreads();
+        }
     }
     T *U = (D == 3) ? X1 : X0;
     T *Wk = (D == 3) ? X0 : X1;
 
     // 3. collocation gradients d/dxi of the stored fields
     if (GRAD) {
-        axis_pass<P, D, 0, T, M_D, false>(U, cs_x, G, cs_g, C, F);
-        axis_pass<P, D, 1, T, M_D, false>(U, cs_x, G + F * NP, cs_g, C, F);
-        if (D == 3) axis_pass<P, D, (D == 3 ? 2 : 0), T, M_D, false>(U, cs_x, G + 2 * F * NP, cs_g, C, F);
+        axis_pass<P, D, 0, T, M_D, false, F>(U, cs_x, G, cs_g, C);
+        axis_pass<P, D, 1, T, M_D, false, F>(U, cs_x, G + F * NP, cs_g, C);
+        if (D == 3) axis_pass<P, D, (D == 3 ? 2 : 0), T, M_D, false, F>(U, cs_x, G + 2 * F * NP, cs_g, C);
         __syncthreads();
     }
 
@@ -515,10 +584,13 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
     const T gamma = (T)ph.gamma;
     for (int q = tid; q < C * NP; q += nt) {
         const int c = q / NP, j = q - c * NP;
-        T u[MAXF];
+        T u[F + D];
 #pragma unroll
-        for (int f = 0; f < 2 * D + 3; ++f)
-            if (f < Fx) u[f] = U[c * cs_x + f * NP + j];
+        for (int f = 0; f < F; ++f) u[f] = U[c * cs_x + f * NP + j];
+        if (forced) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) u[F + i] = U[c * cs_x + (F + i) * NP + j];
+        }
         int jr = j;
         T wq = T(1);
 #pragma unroll
@@ -532,11 +604,10 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
 #pragma unroll
             for (int b = 0; b < D; ++b)
 #pragma unroll
-                for (int f = 0; f < D + 3; ++f)
-                    if (f < F) g[b][f] = G[c * cs_g + (b * F + f) * NP + j] * (T)ph.two_over_h;
+                for (int f = 0; f < F; ++f) g[b][f] = G[c * cs_g + (b * F + f) * NP + j] * (T)ph.two_over_h;
         }
         T eps = T(0), cs = T(0);
-        if (ph.av_on) {
+        if (PH == 2) {
             cs = sqrt(gamma * s.p * s.ir);
             eps = (T)ph.av_scale * clamp_alpha(u[Fc], (T)ph.alpha_max) * cs * (T)ph.eps_fac;
         }
@@ -544,13 +615,13 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
         for (int b = 0; b < D; ++b) {
             T fl[D + 2];
             euler_flux<D, T>(u, s, b, fl);
-            if (GRAD && ph.ns_on) {
+            if (PH == 1 || (PH == 2 && ph.ns_on)) {
                 T fv[D + 2];
                 ns_flux<D, T>(u, s, g, b, gamma, (T)ph.nu, (T)ph.kappa, fv);
 #pragma unroll
                 for (int f = 0; f < D + 2; ++f) fl[f] -= fv[f];
             }
-            if (GRAD && ph.av_on) {
+            if (PH == 2) {
 #pragma unroll
                 for (int f = 0; f < D + 2; ++f) fl[f] -= eps * g[b][f];
             }
@@ -562,40 +633,34 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
         T src[D + 2];
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) src[f] = T(0);
-        if (a.forcing) {
-            // the forcing fields follow the stored ones: index F = Fc + av_on
-            T sf[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) sf[i] = ph.av_on ? u[D + 3 + i] : u[D + 2 + i];
+        if (forced) {
             T sv = T(0);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                src[1 + i] = s.rho * sf[i];
-                sv += sf[i] * u[1 + i];
+                src[1 + i] = s.rho * u[F + i];
+                sv += u[F + i] * u[1 + i];
             }
             src[D + 1] = sv;
         }
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) U[c * cs_x + f * NP + j] = hw * src[f];
-        if (ph.av_on) {
+        if (PH == 2) {
             T div = T(0);
-            if (GRAD) {
 #pragma unroll
-                for (int i = 0; i < D; ++i) div += (g[i][1 + i] - s.v[i] * g[i][0]) * s.ir;
-            }
-            const T asrc = (T)ph.f_v * fmax(T(0), -div) + (T)cellv[2 * c] - u[Fc] * cs * (T)ph.sink;
+            for (int i = 0; i < D; ++i) div += (g[i][1 + i] - s.v[i] * g[i][0]) * s.ir;
+            const T asrc = (T)ph.f_v * fmax(T(0), -div) + (T)cellv[c] - u[Fc] * cs * (T)ph.sink;
             U[c * cs_x + Fc * NP + j] = hw * asrc;
         }
     }
     __syncthreads();
 
     // 5. Q += sum_a D_a^T (w f_a)
-    axis_pass<P, D, 0, T, M_DT, true>(G, cs_g, U, cs_x, C, Fc);
+    axis_pass<P, D, 0, T, M_DT, true, Fc>(G, cs_g, U, cs_x, C);
     __syncthreads();
-    axis_pass<P, D, 1, T, M_DT, true>(G + F * NP, cs_g, U, cs_x, C, Fc);
+    axis_pass<P, D, 1, T, M_DT, true, Fc>(G + F * NP, cs_g, U, cs_x, C);
     __syncthreads();
     if (D == 3) {
-        axis_pass<P, D, (D == 3 ? 2 : 0), T, M_DT, true>(G + 2 * F * NP, cs_g, U, cs_x, C, Fc);
+        axis_pass<P, D, (D == 3 ? 2 : 0), T, M_DT, true, Fc>(G + 2 * F * NP, cs_g, U, cs_x, C);
         __syncthreads();
     }
 
@@ -608,28 +673,7 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
             const int c = q / (Fc * K);
             const int r = q - c * (Fc * K);
             const int f = r / K, k = r - f * K;
-            long long cc = c0 + c;
-            if (cc >= NC) cc = NC - 1;
-            // face indices of the lower and upper face of cell cc along ax
-            int co[3] = {0, 0, 0};
-            long long t = cc;
-            for (int b = 0; b < 3; ++b) {
-                co[b] = (int)(t % geo.n[b]);
-                t /= geo.n[b];
-            }
-            const int nfa = geo.nf[ax];
-            long long flo = 0, fhi = 0, mul = 1;
-            for (int b = 0; b < 3; ++b) {
-                const int nb = (b == ax) ? nfa : geo.n[b];
-                int ilo = co[b], ihi = co[b];
-                if (b == ax) {
-                    ihi = co[b] + 1;
-                    if (ihi >= nfa) ihi -= nfa;    // periodic wrap (outflow has nf = n + 1)
-                }
-                flo += ilo * mul;
-                fhi += ihi * mul;
-                mul *= nb;
-            }
+            const long long flo = fidx[(c * D + ax) * 2], fhi = fidx[(c * D + ax) * 2 + 1];
             const T Fl = fb[flo * (Fc * K) + f * K + k];
             const T Fu = fb[fhi * (Fc * K) + f * K + k];
             const int lo = k % S, hi = k / S;
@@ -641,12 +685,12 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
     }
 
     // 7. point -> modal projection of every stored field
-    axis_pass<P, D, 0, T, M_BT, false>(U, cs_x, Wk, cs_x, C, F);
+    axis_pass<P, D, 0, T, M_BT, false, F>(U, cs_x, Wk, cs_x, C);
     __syncthreads();
-    axis_pass<P, D, 1, T, M_BT, false>(Wk, cs_x, U, cs_x, C, F);
+    axis_pass<P, D, 1, T, M_BT, false, F>(Wk, cs_x, U, cs_x, C);
     __syncthreads();
     if (D == 3) {
-        axis_pass<P, D, (D == 3 ? 2 : 0), T, M_BT, false>(U, cs_x, Wk, cs_x, C, F);
+        axis_pass<P, D, (D == 3 ? 2 : 0), T, M_BT, false, F>(U, cs_x, Wk, cs_x, C);
         __syncthreads();
     }
     const T *V = (D == 3) ? Wk : U;
@@ -655,75 +699,74 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
     const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
     const double pref = ph.pref;
     int bad = 0;
-    for (int i = tid; i < C * F * NP; i += nt) {
-        const int c = i / (F * NP), r = i - c * (F * NP);
+    for (int i = tid; i < C * FNP; i += nt) {
+        const int c = i / FNP, r = i - c * FNP;
         const long long gi = gbase + i;
         if (gi >= gend) continue;
         const double L = pref * (double)V[c * cs_x + r];
         const double cur = a.cur[gi];
         double o = a.c_cur * cur + a.c_L * dt * L;
         if (a.base) o += a.c_base * a.base[gi];
-        double o2 = 0.0;
         if (a.out2) {
-            o2 = a.d_cur * cur + a.d_L * dt * L;
+            double o2 = a.d_cur * cur + a.d_L * dt * L;
             if (a.x2) o2 += a.d_x2 * a.x2[gi];
+            a.out2[gi] = o2;
         }
         a.out[gi] = o;
-        if (a.out2) a.out2[gi] = o2;
         if (!isfinite(o)) bad |= 2;
     }
     if (bad) atomicOr(blkflag, bad);
     __syncthreads();
 
-    // 9. per-cell checks (mean pressure) and, at stage 1, d ln S / dt
+    // 9. per-cell checks (mean density and pressure) and, at stage 1, d ln S / dt
     for (int cl = tid; cl < C; cl += nt) {
         const long long cc = c0 + cl;
-        if (cc < NC) {
-            const double *o = a.out + cc * F * NP;
-            const double rho = o[0];
-            double m2 = 0.0;
-            for (int i = 0; i < D; ++i) m2 += o[(1 + i) * NP] * o[(1 + i) * NP];
-            const double pm = (ph.gamma - 1.0) * (o[(D + 1) * NP] - 0.5 * m2 / rho);
-            if (a.check && !(rho > 0.0 && pm > 0.0)) atomicOr(blkflag, 1);
-            if (a.R_out && ph.av_on) {
-                const double *wr = a.cur + cc * F * NP;
-                double A = 0.0, Tt = 0.0, ad = 0.0, td = 0.0;
-                for (int m = 0; m < NP; ++m) {
-                    const double x = wr[m];
-                    const double xd = pref * (double)V[cl * cs_x + m];
-                    A += x * x;
-                    ad += x * xd;
-                    bool t = false;
-                    int r = m;
-                    for (int b = 0; b < D; ++b) {
-                        t = t || (r % P == P - 1);
-                        r /= P;
-                    }
-                    if (t) {
-                        Tt += x * x;
-                        td += x * xd;
-                    }
+        if (cc >= NC) continue;
+        const double *o = a.out + cc * FNP;
+        const double rho = o[0];
+        double m2 = 0.0;
+        for (int i = 0; i < D; ++i) m2 += o[(1 + i) * NP] * o[(1 + i) * NP];
+        const double pm = (ph.gamma - 1.0) * (o[(D + 1) * NP] - 0.5 * m2 / rho);
+        if (a.check && !(rho > 0.0 && pm > 0.0)) atomicOr(blkflag, 1);
+        if (PH == 2 && a.R_out) {
+            const double *wr = a.cur + cc * FNP;
+            double Aa = 0.0, Tt = 0.0, ad = 0.0, td = 0.0;
+            for (int m = 0; m < NP; ++m) {
+                const double x = wr[m];
+                const double xd = pref * (double)V[cl * cs_x + m];
+                Aa += x * x;
+                ad += x * xd;
+                bool tp = false;
+                int r = m;
+                for (int b = 0; b < D; ++b) {
+                    tp = tp || (r % P == P - 1);
+                    r /= P;
                 }
-                double R = 0.0;
-                // rate kept only above the onset threshold (below it S is noise)
-                if (A > 0.0 && Tt > 0.0 && Tt / A > ph.s_thr) {
-                    const double S = Tt / A;
-                    const double Sdot = 2.0 * (td * A - Tt * ad) / (A * A);
-                    R = Sdot / S;
+                if (tp) {
+                    Tt += x * x;
+                    td += x * xd;
                 }
-                a.R_out[cc] = R;
             }
+            double R = 0.0;
+            // rate kept only above the onset threshold (below it S is noise)
+            if (Aa > 0.0 && Tt > 0.0 && Tt / Aa > ph.s_thr) {
+                const double Sv = Tt / Aa;
+                const double Sdot = 2.0 * (td * Aa - Tt * ad) / (Aa * Aa);
+                R = Sdot / Sv;
+            }
+            a.R_out[cc] = R;
         }
     }
     __syncthreads();
     if (tid == 0 && *blkflag && a.flag) atomicOr(a.flag, *blkflag);
 }
 
-template <int D, int P, typename T>
-size_t vol_lds_bytes(int C, int F, int Fx)
+template <int D, int P, typename T, int PH>
+size_t vol_lds_bytes(int C, int Fx)
 {
     constexpr int NP = ipow(P, D);
-    const size_t hdr = ((2 * C * sizeof(double) + sizeof(int) + 15) / 16) * 16;
+    constexpr int F = Fld<D, PH>::F;
+    const size_t hdr = ((C * (2 * D * sizeof(long long) + sizeof(double)) + sizeof(int) + 15) / 16) * 16;
     return hdr + sizeof(T) * ((size_t)2 * C * Fx * NP + (size_t)C * D * F * NP);
 }
 
@@ -731,13 +774,15 @@ size_t vol_lds_bytes(int C, int F, int Fx)
 // CFL kernel: maxima of c_s and |v| over the volume Gauss points (eq. timestep)
 // ---------------------------------------------------------------------------
 
-template <int D, int P>
+__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+template <int D, int P, int PH>
 __global__ void __launch_bounds__(512) cfl_kernel(Phys ph, Geo geo, CflArgs a)
 {
     constexpr int NP = ipow(P, D);
+    constexpr int Fc = D + 2;
+    constexpr int FNP = Fld<D, PH>::F * NP;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Fc = D + 2;
-    const int F = Fc + ph.av_on;
     const int C = a.cells_per_block;
     const int tid = threadIdx.x, nt = blockDim.x;
     const long long NC = geo.ncells;
@@ -749,15 +794,15 @@ __global__ void __launch_bounds__(512) cfl_kernel(Phys ph, Geo geo, CflArgs a)
         const int c = i / (Fc * NP), r = i - c * (Fc * NP);
         long long cc = c0 + c;
         if (cc >= NC) cc = NC - 1;
-        X0[i] = a.w[cc * F * NP + r];
+        X0[i] = a.w[cc * FNP + r];
     }
     __syncthreads();
-    axis_pass<P, D, 0, double, M_B, false>(X0, Fc * NP, X1, Fc * NP, C, Fc);
+    axis_pass<P, D, 0, double, M_B, false, Fc>(X0, Fc * NP, X1, Fc * NP, C);
     __syncthreads();
-    axis_pass<P, D, 1, double, M_B, false>(X1, Fc * NP, X0, Fc * NP, C, Fc);
+    axis_pass<P, D, 1, double, M_B, false, Fc>(X1, Fc * NP, X0, Fc * NP, C);
     __syncthreads();
     if (D == 3) {
-        axis_pass<P, D, (D == 3 ? 2 : 0), double, M_B, false>(X0, Fc * NP, X1, Fc * NP, C, Fc);
+        axis_pass<P, D, (D == 3 ? 2 : 0), double, M_B, false, Fc>(X0, Fc * NP, X1, Fc * NP, C);
         __syncthreads();
     }
     const double *U = (D == 3) ? X1 : X0;
@@ -772,27 +817,22 @@ __global__ void __launch_bounds__(512) cfl_kernel(Phys ph, Geo geo, CflArgs a)
         double v2 = 0.0;
 #pragma unroll
         for (int i = 0; i < D; ++i) v2 += s.v[i] * s.v[i];
-        const double cs = sqrt(ph.gamma * s.p * s.ir);
-        const double vm = sqrt(v2);
-        // NaN-propagating maxima (a NaN makes the step size NaN)
-        cmax = (cs > cmax || cs != cs) ? cs : cmax;
-        vmax = (vm > vmax || vm != vm) ? vm : vmax;
+        cmax = nanmax(cmax, sqrt(ph.gamma * s.p * s.ir));   // NaN propagates into dt
+        vmax = nanmax(vmax, sqrt(v2));
     }
     red[tid] = cmax;
     red[nt + tid] = vmax;
     __syncthreads();
     for (int s = nt / 2; s > 0; s >>= 1) {
         if (tid < s) {
-            const double c2 = red[tid + s], v2 = red[nt + tid + s];
-            if (c2 > red[tid] || c2 != c2) red[tid] = c2;
-            if (v2 > red[nt + tid] || v2 != v2) red[nt + tid] = v2;
+            red[tid] = nanmax(red[tid], red[tid + s]);
+            red[nt + tid] = nanmax(red[nt + tid], red[nt + tid + s]);
         }
         __syncthreads();
     }
     if (tid == 0) {
-        // non-negative doubles order like their bit patterns
-        atomicMax(&a.maxbits[0], (unsigned long long)__double_as_longlong(red[0]));
-        atomicMax(&a.maxbits[1], (unsigned long long)__double_as_longlong(red[nt]));
+        a.part[2 * blockIdx.x] = red[0];
+        a.part[2 * blockIdx.x + 1] = red[nt];
     }
 }
 

@@ -6,22 +6,22 @@
 
 namespace dgk {
 
-// Kernels and LDS-size functions of one (dim, order, precision, gradient)
-// instantiation.  The function pointers are the host stubs of __global__
+// Kernels and LDS-size functions of one (dim, order, precision, physics)
+// instantiation; physics PH = 0 Euler, 1 Navier-Stokes, 2 artificial viscosity.  The function pointers are the host stubs of __global__
 // functions, launched with hipLaunchKernel.
 struct KernelSet {
     const void *vol;
     const void *face;
     const void *cfl;   // FP64 units only
-    size_t (*vol_lds)(int C, int F, int Fx);
-    size_t (*face_lds)(int C, int F);
+    size_t (*vol_lds)(int C, int Fx);
+    size_t (*face_lds)(int C);
     size_t (*cfl_lds)(int C, int nt);
 };
 
-void dgk_get_2d_f64(int P, bool grad, KernelSet *k);
-void dgk_get_3d_f64(int P, bool grad, KernelSet *k);
-void dgk_get_2d_f32(int P, bool grad, KernelSet *k);
-void dgk_get_3d_f32(int P, bool grad, KernelSet *k);
+void dgk_get_2d_f64(int P, int ph, KernelSet *k);
+void dgk_get_3d_f64(int P, int ph, KernelSet *k);
+void dgk_get_2d_f32(int P, int ph, KernelSet *k);
+void dgk_get_3d_f32(int P, int ph, KernelSet *k);
 int dgk_upload_2d_f64(const Tab<double> *d, const Tab<float> *f);
 int dgk_upload_3d_f64(const Tab<double> *d, const Tab<float> *f);
 int dgk_upload_2d_f32(const Tab<double> *d, const Tab<float> *f);
