@@ -19,7 +19,10 @@ Extra objects on the JSON line:
                of the same workload;
   fp32_bulk    the same workload with FP32 bulk arithmetic (FP64 state/RK);
   turbulence_3d  the 3D driven-turbulence box, 128^3, p = 4 (FP64), with its
-               own roofline record.
+               own roofline record;
+  ensemble     48 independent 2D boxes (sides 32..512, orders 2..6) stepped by
+               grouped launches replayed from one hipGraph, against the same
+               steps issued box by box.
 """
 import argparse
 import hashlib
@@ -202,6 +205,42 @@ def measure(name, order, precision, steps, warmup, device="cuda"):
     return res
 
 
+def measure_ensemble(steps, warmup):
+    sides, orders = W.ensemble_layout(48)
+    ws = [W.ensemble_box(b, sides[b], orders[b], device="cuda") for b in range(48)]
+    w2 = [w.clone() for w in ws]
+    bt = dg.Batch(2, sides, orders, 5.0 / 3.0, cfl=0.5)
+    stages = [1 if p == 1 else 2 if p == 2 else 3 if p == 3 else 5 for p in orders]
+    work = sum(w.numel() * s for w, s in zip(ws, stages))
+    for _ in range(warmup):
+        bt.step(ws)
+        for i in range(48):
+            bt.box_step_cfl(i, w2[i])
+    torch.cuda.synchronize()
+    res = {}
+    for mode in ("graph", "per_box"):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            if mode == "graph":
+                bt.step(ws)
+            else:
+                for i in range(48):
+                    bt.box_step_cfl(i, w2[i])
+        e1.record()
+        torch.cuda.synchronize()
+        res[mode] = e0.elapsed_time(e1) / steps
+    for i in range(48):
+        if bt.box_check(i) != 0:
+            raise RuntimeError("ensemble box %d produced a non-physical state" % i)
+    same = all(torch.equal(a, b) for a, b in zip(ws, w2))
+    dofs = sum(w.numel() for w in ws)
+    return {"value": work / (res["graph"] * 1e-3), "unit": "DOF-updates/s", "ms_per_step": res["graph"],
+            "per_box_ms_per_step": res["per_box"], "speedup_vs_per_box": res["per_box"] / res["graph"],
+            "boxes": 48, "dofs": dofs, "orders": orders, "sides": sides, "bitwise_equal_to_per_box": same}
+
+
 def traffic_record(kernel, workload):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
     were taken on the current kernel sources; else None."""
@@ -296,6 +335,9 @@ def main():
                                               "achieved": d3["achieved"], "peak": d3["peak"], "unit": d3["unit"],
                                               "frac": d3["frac"], "avg_us": d3["avg_us"]}}
         del r3
+        torch.cuda.empty_cache()
+        print("bench: ensemble", file=sys.stderr, flush=True)
+        line["ensemble"] = measure_ensemble(5, 1)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -166,6 +166,38 @@ dg_status dg_timing_enable(dg_ctx *ctx, int on);
 dg_status dg_timing_read(dg_ctx *ctx, double *face_ms, long long *face_n, double *vol_ms, long long *vol_n,
                          double *cfl_ms, long long *cfl_n, long long *dropped);
 
+/* ---------------------------------------------------------------------------
+ * Batched ensembles: many independent boxes (own mesh size and order, same
+ * dimension and physics) advanced together.  Boxes are grouped by order; each
+ * group runs one grouped launch per kernel kind and RK stage over all of its
+ * boxes (a device table maps flat blocks to (box, tile)), and the whole step
+ * of every group is captured once into a hipGraph and replayed.
+ * ------------------------------------------------------------------------- */
+typedef struct dg_batch dg_batch;
+
+/* nbox boxes, meshes[i] / orders[i] per box (same dim for all; each box
+ * validated as by dg_init).  gamma, nu, kappa as dg_init; av must be NULL or
+ * disabled (DG_EUNSUPPORTED otherwise).  Allocates every box's registers. */
+dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, double gamma, double nu, double kappa,
+                        const dg_av_params *av, const dg_options *opt, dg_batch **out);
+void dg_batch_free(dg_batch *b);
+
+/* One SSP-RK step of every box i (its own scheme by order), in place on the
+ * device arrays w[i] (host array of nbox device pointers), each with its own
+ * CFL time step computed on the device (eq. timestep).  The first call (and
+ * any call with different pointers) captures the step into a hipGraph on
+ * `stream`; later calls replay it.  use_graph = 0 launches the same grouped
+ * kernels without a graph. */
+dg_status dg_batch_step(dg_batch *b, double *const *w, int use_graph, void *stream);
+
+/* Per-box step sizes of the last batched step (host array of nbox doubles).
+ * Synchronises `stream`. */
+dg_status dg_batch_dt(dg_batch *b, double *dt_out, void *stream);
+
+/* The context of box i (e.g. for per-box dg_step_cfl launches on the same
+ * buffers, dg_rhs, totals).  Owned by the batch. */
+dg_status dg_batch_box(dg_batch *b, int i, dg_ctx **ctx);
+
 const char *dg_status_str(dg_status s);
 
 #ifdef __cplusplus

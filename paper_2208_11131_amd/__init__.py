@@ -68,6 +68,13 @@ _SIGS = {
     "dg_timing_read": (ctypes.c_int, [_V, _D, ctypes.POINTER(ctypes.c_longlong), _D,
                                       ctypes.POINTER(ctypes.c_longlong), _D, ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_longlong)]),
+    "dg_batch_init": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(dg_mesh), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.POINTER(dg_av_params), ctypes.POINTER(dg_options), ctypes.POINTER(_V)]),
+    "dg_batch_free": (None, [_V]),
+    "dg_batch_step": (ctypes.c_int, [_V, ctypes.POINTER(_V), ctypes.c_int, _V]),
+    "dg_batch_dt": (ctypes.c_int, [_V, _D, _V]),
+    "dg_batch_box": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(_V)]),
     "dg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
 }
 EXPORTS = tuple(_SIGS)
@@ -229,6 +236,73 @@ def dg_timing_read(ctx):
                               ctypes.byref(n[3])), "dg_timing_read")
     return {"face": (d[0].value, n[0].value), "vol": (d[1].value, n[1].value),
             "cfl": (d[2].value, n[2].value), "dropped": n[3].value}
+
+
+def dg_batch_init(meshes, orders, gamma, nu=0.0, kappa=0.0, av=None, opt=None):
+    n = len(meshes)
+    arr = (dg_mesh * n)(*meshes)
+    ords = (ctypes.c_int * n)(*orders)
+    b = _V()
+    _chk(lib().dg_batch_init(n, arr, ords, gamma, nu, kappa, ctypes.byref(av) if av is not None else None,
+                             ctypes.byref(opt) if opt is not None else None, ctypes.byref(b)), "dg_batch_init")
+    return b
+
+
+def dg_batch_free(b):
+    lib().dg_batch_free(b)
+
+
+def dg_batch_step(b, ws, use_graph=True, stream=None):
+    ptrs = (_V * len(ws))(*[_dptr(w) for w in ws])
+    _chk(lib().dg_batch_step(b, ptrs, 1 if use_graph else 0, _stream(stream)), "dg_batch_step")
+
+
+def dg_batch_dt(b, nbox, stream=None):
+    out = (ctypes.c_double * nbox)()
+    _chk(lib().dg_batch_dt(b, out, _stream(stream)), "dg_batch_dt")
+    return list(out)
+
+
+def dg_batch_box(b, i):
+    c = _V()
+    _chk(lib().dg_batch_box(b, i, ctypes.byref(c)), "dg_batch_box")
+    return c
+
+
+class Batch:
+    """Ensemble of independent 2D/3D boxes advanced by grouped launches
+    replayed from a captured hipGraph (one dg_batch)."""
+
+    def __init__(self, dim, sides, orders, gamma, nu=0.0, kappa=0.0, cfl=0.5):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the DG library runs on the GPU only")
+        self.dim = dim
+        self.meshes = [make_mesh(dim, [sd] * dim, hi=[1.0] * dim) for sd in sides]
+        opt = dg_options_defaults()
+        opt.cfl = cfl
+        self.orders = list(orders)
+        self.sides = list(sides)
+        self.b = dg_batch_init(self.meshes, self.orders, gamma, nu, kappa, None, opt)
+        self.nbox = len(sides)
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b:
+            dg_batch_free(b)
+            self.b = None
+
+    def step(self, ws, use_graph=True, stream=None):
+        dg_batch_step(self.b, ws, use_graph, stream)
+
+    def dts(self, stream=None):
+        return dg_batch_dt(self.b, self.nbox, stream)
+
+    def box_step_cfl(self, i, w, stream=None):
+        """Per-box launch of the same step on box i's own buffers."""
+        dg_step_cfl(dg_batch_box(self.b, i), w, None, stream)
+
+    def box_check(self, i, stream=None):
+        return dg_check(dg_batch_box(self.b, i), stream)
 
 
 # ---------------------------------------------------------------------------

@@ -37,6 +37,7 @@ struct Phys {
     int av_on;           // AV field present
     double av_scale, f_v, sink;   // sink = p/(f_tau h): alpha/tau = alpha c_s sink
     double f_w, s_thr, alpha_max, eps_fac;   // s_thr = s_onset/p^2, eps_fac = h/p
+    int order;           // p
 };
 
 // Mesh geometry.  Face space of direction a has nf[a] planes along a
@@ -80,6 +81,30 @@ struct CflArgs {
     const double *w;
     double *part;          // [block][2]: c_s max, |v| max of each block
     int cells_per_block;
+};
+
+// One box of a batched ensemble (device table, one entry per box of a
+// (dim, order) group).  reg[0] is the caller's state, reg[1..3] the RK
+// registers; start[k] = first flat block of this box in the grouped launch of
+// kind k (0 volume, 1 face, 2 CFL).
+struct BoxDesc {
+    Phys ph;
+    Geo geo;
+    double *reg[4];
+    void *fb;
+    double *cfl_part;
+    double *dt;          // [0] dt, [1] c_max, [2] v_max of the box
+    int *flag;
+    long long start[3];
+    long long nblocks[3];
+    int cells_per_block, faces_per_block, cfl_cells, pad;
+};
+
+// RK stage of a grouped launch: register roles (-1 = none) and Shu-Osher
+// coefficients, shared by every box of the group (same order, same scheme).
+struct StageDesc {
+    int cur, base, x2, out, out2;
+    double c_base, c_cur, c_L, d_x2, d_cur, d_L;
 };
 
 // Number of face blocks (grid.x) for pencils of C faces: the largest over the

@@ -238,6 +238,36 @@ __global__ void cfl_finalize(const double *part, int nblk, double *res, double *
     }
 }
 
+// Per-box CFL reduction of a grouped launch: block i reduces box i's partials.
+__global__ void cfl_finalize_batched(const dgk::BoxDesc *boxes, double cfl)
+{
+    __shared__ double rc[256], rv[256];
+    const dgk::BoxDesc &B = boxes[blockIdx.x];
+    const int t = threadIdx.x;
+    const long long nb = B.nblocks[2];
+    double c = 0.0, v = 0.0;
+    for (long long k = t; k < nb; k += blockDim.x) {
+        c = nanmax2(c, B.cfl_part[2 * k]);
+        v = nanmax2(v, B.cfl_part[2 * k + 1]);
+    }
+    rc[t] = c;
+    rv[t] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+            rc[t] = nanmax2(rc[t], rc[t + s]);
+            rv[t] = nanmax2(rv[t], rv[t + s]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double num = cfl * B.ph.h / (2.0 * B.ph.order);
+        B.dt[0] = num / (rc[0] + rv[0]);
+        B.dt[1] = rc[0];
+        B.dt[2] = rv[0];
+    }
+}
+
 // Neumaier-compensated add of x into (s, c).
 __device__ __forceinline__ void nadd(double &s, double &c, double x)
 {
@@ -374,7 +404,7 @@ dg_status launch(dg_ctx *c, int kind, const void *fn, dim3 grid, dim3 block, voi
             }
             e0 = (*c->ev_pool)[2 * c->ev_used];
             e1 = (*c->ev_pool)[2 * c->ev_used + 1];
-            c->ev_kind->push_back(kind);
+            c->ev_kind->push_back(kind > 2 ? 2 : kind);
             ++c->ev_used;
             if (!ok(hipEventRecord(e0, s))) return DG_EDEVICE;
         } else {
@@ -423,9 +453,12 @@ dg_status run_cfl(dg_ctx *c, const double *w, double *dt_copy, hipStream_t s)
     dim3 g((unsigned)c->cfl_blocks);
     dg_status st = launch(c, 2, c->ks64.cfl, g, dim3(c->cfl_T), args, c->cfl_lds, s);
     if (st != DG_OK) return st;
-    const double num = c->cfl * c->ph.h / (2.0 * c->P);
-    hipLaunchKernelGGL(cfl_finalize, dim3(1), dim3(256), 0, s, c->cfl_part, c->cfl_blocks, c->scal, dt_copy, num);
-    return ok(hipGetLastError()) ? DG_OK : DG_EDEVICE;
+    double num = c->cfl * c->ph.h / (2.0 * c->P);
+    const double *part = c->cfl_part;
+    int nblk = c->cfl_blocks;
+    double *res = c->scal;
+    void *fargs[] = {&part, &nblk, &res, &dt_copy, &num};
+    return launch(c, 3, (const void *)&cfl_finalize, dim3(1), dim3(256), fargs, 0, s);
 }
 
 // SSP-RK step in Shu-Osher form; dt from the host value or a device pointer.
@@ -610,6 +643,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     c->fb_bytes = (size_t)off * tsz;
 
     dgk::Phys &ph = c->ph;
+    ph.order = order;
     ph.gamma = gamma;
     ph.nu = nu;
     ph.kappa = kappa;
@@ -814,10 +848,18 @@ dg_status dg_conserved_totals(dg_ctx *c, const double *w, double *out, void *str
     hipStream_t s = (hipStream_t)stream;
     double vol = 1.0;
     for (int a = 0; a < c->dim; ++a) vol *= c->ph.h;
-    hipLaunchKernelGGL(totals_partial, dim3(c->tot_blocks), dim3(256), 0, s, w, c->ncells, c->F, c->NP, c->Fc, vol,
-                       c->tot_chunk, c->tot_part);
-    hipLaunchKernelGGL(totals_final, dim3(1), dim3(64), 0, s, c->tot_part, c->tot_blocks, c->Fc, c->scal + 3);
-    if (!ok(hipGetLastError())) return DG_EDEVICE;
+    {
+        long long nc = c->ncells;
+        int F = c->F, NP = c->NP, Fc = c->Fc, chunk = c->tot_chunk;
+        double *part = c->tot_part;
+        void *a1[] = {(void *)&w, &nc, &F, &NP, &Fc, &vol, &chunk, &part};
+        if (!ok(hipLaunchKernel((const void *)&totals_partial, dim3(c->tot_blocks), dim3(256), a1, 0, s)))
+            return DG_EDEVICE;
+        int nb = c->tot_blocks;
+        double *o = c->scal + 3;
+        void *a2[] = {&part, &nb, &Fc, &o};
+        if (!ok(hipLaunchKernel((const void *)&totals_final, dim3(1), dim3(64), a2, 0, s))) return DG_EDEVICE;
+    }
     if (!ok(hipMemcpyAsync(out, c->scal + 3, c->Fc * sizeof(double), hipMemcpyDeviceToHost, s))) return DG_EDEVICE;
     if (!ok(hipStreamSynchronize(s))) return DG_EDEVICE;
     return DG_OK;
@@ -872,6 +914,294 @@ dg_status dg_get_tiles(const dg_ctx *c, int *vol_cells, int *vol_threads, int *f
     if (vol_threads) *vol_threads = c->vol_T;
     if (face_cells) *face_cells = c->face_C;
     if (face_threads) *face_threads = c->face_T;
+    return DG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched ensembles
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Group {
+    int P = 0;
+    std::vector<int> boxes;                 // box ids of this order
+    std::vector<dgk::BoxDesc> h_desc;
+    dgk::BoxDesc *d_desc = nullptr;
+    KernelSet ks{}, ks64{};
+    long long nblk[3] = {0, 0, 0};          // total flat blocks per kind
+    int vol_T = 0, face_T = 0, cfl_T = 0;
+    size_t vol_lds = 0, face_lds = 0, cfl_lds = 0;
+    int stages = 0;
+};
+
+}  // namespace
+
+struct dg_batch {
+    int nbox = 0, dim = 0;
+    double cfl = 0.5;
+    std::vector<dg_ctx *> box;
+    std::vector<Group> groups;
+    std::vector<double *> wptr;
+    bool have_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;     // private stream for graph capture
+};
+
+namespace {
+
+void batch_release(dg_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (Group &g : b->groups)
+        if (g.d_desc) (void)hipFree(g.d_desc);
+    for (dg_ctx *c : b->box) dg_free(c);
+}
+
+// Shu-Osher stage table for a scheme with S stages, register roles
+// (0 = state, 1..3 = RK registers), identical to rk_step.
+int stage_table(int S, dgk::StageDesc *sd)
+{
+    auto mk = [](int cur, int base, int out, double cb, double cc, double cl) {
+        dgk::StageDesc d;
+        d.cur = cur;
+        d.base = base;
+        d.x2 = -1;
+        d.out = out;
+        d.out2 = -1;
+        d.c_base = cb;
+        d.c_cur = cc;
+        d.c_L = cl;
+        d.d_x2 = d.d_cur = d.d_L = 0.0;
+        return d;
+    };
+    if (S == 1) {
+        sd[0] = mk(0, -1, 0, 0.0, 1.0, 1.0);
+        return 1;
+    }
+    if (S == 2) {
+        sd[0] = mk(0, -1, 1, 0.0, 1.0, 1.0);
+        sd[1] = mk(1, 0, 0, 0.5, 0.5, 0.5);
+        return 2;
+    }
+    if (S == 3) {
+        sd[0] = mk(0, -1, 1, 0.0, 1.0, 1.0);
+        sd[1] = mk(1, 0, 2, 0.75, 0.25, 0.25);
+        sd[2] = mk(2, 0, 0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0);
+        return 3;
+    }
+    sd[0] = mk(0, -1, 1, 0.0, 1.0, 0.391752226571890);
+    sd[1] = mk(1, 0, 2, 0.444370493651235, 0.555629506348765, 0.368410593050371);
+    sd[2] = mk(2, 0, 3, 0.620101851488403, 0.379898148511597, 0.251891774271694);
+    sd[3] = mk(3, 0, 1, 0.178079954393132, 0.821920045606868, 0.544974750228521);
+    sd[3].out2 = 0;
+    sd[3].x2 = 2;
+    sd[3].d_x2 = 0.517231671970585;
+    sd[3].d_cur = 0.096059710526147;
+    sd[3].d_L = 0.063692468666290;
+    sd[4] = mk(1, 0, 0, 1.0, 0.386708617503269, 0.226007483236906);
+    return 5;
+}
+
+dg_status batch_enqueue(dg_batch *b, hipStream_t s)
+{
+    for (Group &g : b->groups) {
+        const int n = (int)g.boxes.size();
+        dgk::BoxDesc *d = g.d_desc;
+        {
+            void *args[] = {&d, (void *)&n};
+            if (!ok(hipLaunchKernel(g.ks64.cfl_b, dim3((unsigned)g.nblk[2]), dim3(g.cfl_T), args, g.cfl_lds, s)))
+                return DG_EDEVICE;
+        }
+        {
+            double cfl = b->cfl;
+            void *args[] = {&d, &cfl};
+            if (!ok(hipLaunchKernel((const void *)&cfl_finalize_batched, dim3(n), dim3(256), args, 0, s)))
+                return DG_EDEVICE;
+        }
+        dgk::StageDesc sd[5];
+        const int S = stage_table(g.stages, sd);
+        for (int k = 0; k < S; ++k) {
+            int cur = sd[k].cur;
+            void *fargs[] = {&d, (void *)&n, &cur};
+            if (!ok(hipLaunchKernel(g.ks.face_b, dim3((unsigned)g.nblk[1]), dim3(g.face_T), fargs, g.face_lds, s)))
+                return DG_EDEVICE;
+            void *vargs[] = {&d, (void *)&n, &sd[k]};
+            if (!ok(hipLaunchKernel(g.ks.vol_b, dim3((unsigned)g.nblk[0]), dim3(g.vol_T), vargs, g.vol_lds, s)))
+                return DG_EDEVICE;
+        }
+    }
+    return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, double gamma, double nu, double kappa,
+                        const dg_av_params *av, const dg_options *opt, dg_batch **out)
+{
+    if (!out) return DG_EINVAL;
+    *out = nullptr;
+    if (nbox < 1 || !meshes || !orders) return DG_EINVAL;
+    if (av && av->enabled) return DG_EUNSUPPORTED;
+    for (int i = 0; i < nbox; ++i)
+        if (meshes[i].dim != meshes[0].dim) return DG_EINVAL;
+    dg_batch *b = new (std::nothrow) dg_batch;
+    if (!b) return DG_ENOMEM;
+    b->nbox = nbox;
+    b->dim = meshes[0].dim;
+    b->cfl = opt ? opt->cfl : 0.5;
+    b->box.assign(nbox, nullptr);
+    b->wptr.assign(nbox, nullptr);
+    for (int i = 0; i < nbox; ++i) {
+        dg_status st = dg_init(&meshes[i], orders[i], gamma, nu, kappa, nullptr, opt, &b->box[i]);
+        if (st != DG_OK) {
+            batch_release(b);
+            delete b;
+            return st;
+        }
+    }
+    for (int P = 1; P <= MAXP; ++P) {
+        Group g;
+        g.P = P;
+        for (int i = 0; i < nbox; ++i)
+            if (orders[i] == P) g.boxes.push_back(i);
+        if (g.boxes.empty()) continue;
+        const dg_ctx *c0 = b->box[g.boxes[0]];
+        g.ks = c0->ks;
+        g.ks64 = c0->ks64;
+        g.vol_T = c0->vol_T;
+        g.face_T = c0->face_T;
+        g.cfl_T = c0->cfl_T;
+        g.vol_lds = c0->vol_lds;
+        g.face_lds = c0->face_lds;
+        g.cfl_lds = c0->cfl_lds;
+        g.stages = c0->stages;
+        if (!g.ks.vol_b || !g.ks.face_b || !g.ks64.cfl_b) {
+            batch_release(b);
+            delete b;
+            return DG_EUNSUPPORTED;
+        }
+        for (int i : g.boxes) {
+            const dg_ctx *c = b->box[i];
+            dgk::BoxDesc d;
+            memset(&d, 0, sizeof(d));
+            d.ph = c->ph;
+            d.geo = c->geo;
+            d.reg[0] = nullptr;
+            for (int r = 0; r < 3; ++r) d.reg[1 + r] = c->reg[r];
+            d.fb = c->fb;
+            d.cfl_part = c->cfl_part;
+            d.dt = c->scal;
+            d.flag = c->flag;
+            d.cells_per_block = c->vol_C;
+            d.faces_per_block = c->face_C;
+            d.cfl_cells = c->cfl_C;
+            d.nblocks[0] = (c->ncells + c->vol_C - 1) / c->vol_C;
+            long long nf = 0;
+            for (int a = 0; a < c->dim; ++a) {
+                long long np = (c->geo.nf[a] + c->face_C - 1) / c->face_C;
+                for (int q = 0; q < 3; ++q)
+                    if (q != a) np *= c->geo.n[q];
+                nf += np;
+            }
+            d.nblocks[1] = nf;
+            d.nblocks[2] = c->cfl_blocks;
+            for (int k = 0; k < 3; ++k) {
+                d.start[k] = g.nblk[k];
+                g.nblk[k] += d.nblocks[k];
+            }
+            g.h_desc.push_back(d);
+        }
+        if (!ok(hipMalloc(&g.d_desc, sizeof(dgk::BoxDesc) * g.h_desc.size()))) {
+            batch_release(b);
+            delete b;
+            return DG_ENOMEM;
+        }
+        b->groups.push_back(g);
+    }
+    *out = b;
+    return DG_OK;
+}
+
+void dg_batch_free(dg_batch *b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    batch_release(b);
+    delete b;
+}
+
+dg_status dg_batch_step(dg_batch *b, double *const *w, int use_graph, void *stream)
+{
+    if (!b || !w) return DG_EINVAL;
+    for (int i = 0; i < b->nbox; ++i)
+        if (!w[i]) return DG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    bool changed = false;
+    for (int i = 0; i < b->nbox; ++i)
+        if (b->wptr[i] != w[i]) changed = true;
+    if (changed) {
+        for (int i = 0; i < b->nbox; ++i) b->wptr[i] = w[i];
+        for (Group &g : b->groups) {
+            for (size_t k = 0; k < g.boxes.size(); ++k) g.h_desc[k].reg[0] = w[g.boxes[k]];
+            if (!ok(hipMemcpyAsync(g.d_desc, g.h_desc.data(), sizeof(dgk::BoxDesc) * g.h_desc.size(),
+                                   hipMemcpyHostToDevice, s)))
+                return DG_EDEVICE;
+        }
+        if (!ok(hipStreamSynchronize(s))) return DG_EDEVICE;
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->have_graph = false;
+    }
+    if (!use_graph) return batch_enqueue(b, s);
+    if (!b->have_graph) {
+        // capture on a private stream (the caller's may be the null stream,
+        // which cannot be captured); the graph is launched on the caller's
+        if (!b->cap && !ok(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking))) return DG_EDEVICE;
+        if (!ok(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed))) return DG_EDEVICE;
+        dg_status st = batch_enqueue(b, b->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &g);
+        if (st != DG_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (!ok(e) || !g) return DG_EDEVICE;
+        hipGraphExec_t ex = nullptr;
+        if (!ok(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0))) {
+            (void)hipGraphDestroy(g);
+            return DG_EDEVICE;
+        }
+        b->graph = g;
+        b->exec = ex;
+        b->have_graph = true;
+    }
+    return ok(hipGraphLaunch(b->exec, s)) ? DG_OK : DG_EDEVICE;
+}
+
+dg_status dg_batch_dt(dg_batch *b, double *dt_out, void *stream)
+{
+    if (!b || !dt_out) return DG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < b->nbox; ++i)
+        if (!ok(hipMemcpyAsync(&dt_out[i], b->box[i]->scal, sizeof(double), hipMemcpyDeviceToHost, s)))
+            return DG_EDEVICE;
+    return ok(hipStreamSynchronize(s)) ? DG_OK : DG_EDEVICE;
+}
+
+dg_status dg_batch_box(dg_batch *b, int i, dg_ctx **ctx)
+{
+    if (!b || !ctx || i < 0 || i >= b->nbox) return DG_EINVAL;
+    *ctx = b->box[i];
     return DG_OK;
 }
 

@@ -11,9 +11,12 @@ void fill(KernelSet *k)
 {
     k->vol = (const void *)&vol_kernel<3, P, float, PH>;
     k->face = (const void *)&face_kernel<3, P, float, PH>;
+    k->vol_b = (const void *)&vol_kernel_batched<3, P, float, PH>;
+    k->face_b = (const void *)&face_kernel_batched<3, P, float, PH>;
     k->vol_lds = &vol_lds_bytes<3, P, float, PH>;
     k->face_lds = &face_lds_bytes<3, P, float, PH>;
     k->cfl = nullptr;
+    k->cfl_b = nullptr;
     k->cfl_lds = nullptr;
 }
 

@@ -86,6 +86,32 @@ __device__ __forceinline__ void axis_pass(const T *__restrict__ in, int in_cs, T
     }
 }
 
+// Apply a p x p operator along axis AX of narr contiguous arrays of p^DA
+// entries.  Line q starts at (q / S) * S * p + q % S (S = p^AX): a couple of
+// integer operations per line; p loads, p*p FMAs with table operands, p stores.
+template <int P, int DA, int AX, typename T, int MAT, bool ACC>
+__device__ __forceinline__ void line_pass(const T *__restrict__ in, T *__restrict__ out, int narr)
+{
+    constexpr int NA = ipow(P, DA);
+    constexpr int S = ipow(P, AX);
+    const int nitems = narr * (NA / P);
+    for (int q = threadIdx.x; q < nitems; q += blockDim.x) {
+        const int off = (q / S) * (S * P) + (q % S);
+        const T *pi = in + off;
+        T *po = out + off;
+        T x[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = pi[k * S];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            T acc = ACC ? po[i * S] : T(0);
+#pragma unroll
+            for (int k = 0; k < P; ++k) acc = fma(mat<P, T, MAT>(k, i), x[k], acc);
+            po[i * S] = acc;
+        }
+    }
+}
+
 // Fields per physics variant: PH = 0 Euler, 1 Navier-Stokes, 2 artificial
 // viscosity (alpha field; Navier-Stokes terms switched at run time).
 template <int D, int PH>
@@ -410,25 +436,68 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     }
 }
 
+// Number of pencils of direction ax (ceil(nf/C) per line times the lines).
+__device__ __forceinline__ long long pencils(const Geo &geo, int ax, int C)
+{
+    long long npen = (geo.nf[ax] + C - 1) / C;
+    for (int b = 0; b < 3; ++b)
+        if (b != ax) npen *= geo.n[b];
+    return npen;
+}
+
+template <int D, int P, typename T, int PH>
+__device__ __forceinline__ void face_dispatch(const Phys &ph, const Geo &geo, const FaceArgs &a, unsigned char *smem,
+                                              int ax, long long pen)
+{
+    if (ax == 0)
+        face_body<D, P, 0, T, PH>(ph, geo, a, smem, pen);
+    else if (ax == 1)
+        face_body<D, P, 1, T, PH>(ph, geo, a, smem, pen);
+    else if (D == 3)
+        face_body<D, P, (D == 3 ? 2 : 0), T, PH>(ph, geo, a, smem, pen);
+}
+
 template <int D, int P, typename T, int PH>
 __global__ void __launch_bounds__(512) face_kernel(Phys ph, Geo geo, FaceArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int ax = blockIdx.y;
-    const int C = a.faces_per_block;
-    // pencils of direction ax: ceil(nf/C) per line, lines = product of the other extents
-    long long npen = (geo.nf[ax] + C - 1) / C;
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-        if (b != ax) npen *= geo.n[b];
     const unsigned bid = xcd_block(blockIdx.x, gridDim.x);
-    if ((long long)bid >= npen) return;
-    if (ax == 0)
-        face_body<D, P, 0, T, PH>(ph, geo, a, smem, bid);
-    else if (ax == 1)
-        face_body<D, P, 1, T, PH>(ph, geo, a, smem, bid);
-    else if (D == 3)
-        face_body<D, P, (D == 3 ? 2 : 0), T, PH>(ph, geo, a, smem, bid);
+    if ((long long)bid >= pencils(geo, ax, a.faces_per_block)) return;
+    face_dispatch<D, P, T, PH>(ph, geo, a, smem, ax, bid);
+}
+
+// Index of the box owning flat block b of a grouped launch (uniform scan).
+__device__ __forceinline__ int owner_box(const BoxDesc *boxes, int nbox, long long b, int which)
+{
+    int i = 0;
+    while (i + 1 < nbox && boxes[i + 1].start[which] <= b) ++i;
+    return i;
+}
+
+// Grouped face kernel: every box of one (dim, order) group; flat block index
+// -> (box, direction, pencil).
+template <int D, int P, typename T, int PH>
+__global__ void __launch_bounds__(512) face_kernel_batched(const BoxDesc *boxes, int nbox, int stage_cur)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const long long b = xcd_block(blockIdx.x, gridDim.x);
+    const int i = owner_box(boxes, nbox, b, 1);
+    const Phys ph = boxes[i].ph;
+    const Geo geo = boxes[i].geo;
+    FaceArgs a;
+    a.w = boxes[i].reg[stage_cur];
+    a.fb = boxes[i].fb;
+    a.faces_per_block = boxes[i].faces_per_block;
+    long long loc = b - boxes[i].start[1];
+    for (int ax = 0; ax < D; ++ax) {
+        const long long n = pencils(geo, ax, a.faces_per_block);
+        if (loc < n) {
+            face_dispatch<D, P, T, PH>(ph, geo, a, smem, ax, loc);
+            return;
+        }
+        loc -= n;
+    }
 }
 
 // LDS bytes of the face kernel for pencils of C faces: slot indices, the C+1
@@ -454,7 +523,8 @@ size_t face_lds_bytes(int C)
 // ---------------------------------------------------------------------------
 
 template <int D, int P, typename T, int PH>
-__global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
+__device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const VolArgs &a, unsigned char *smem,
+                                         long long tile)
 {
     constexpr int NP = ipow(P, D);
     constexpr int K = NP / P;
@@ -462,38 +532,39 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
     constexpr int F = Fld<D, PH>::F;
     constexpr bool GRAD = Fld<D, PH>::GRAD;
     constexpr int FNP = F * NP;
-    extern __shared__ __align__(16) unsigned char smem[];
     const bool forced = a.forcing != nullptr;
     const int Fx = F + (forced ? D : 0);
     const int C = a.cells_per_block;
+    const int CNP = C * NP;                   // one field of the tile
     const int tid = threadIdx.x, nt = blockDim.x;
     const long long NC = geo.ncells;
-    const long long c0 = (long long)xcd_block(blockIdx.x, gridDim.x) * C;
-    const int cs_x = Fx * NP;                 // per-cell stride of X0/X1
-    constexpr int cs_g = D * F * NP;          // per-cell stride of G
+    const long long c0 = tile * C;
 
+    // LDS, field-major: X0/X1 [field][cell][point], G [axis][field][cell][point]
     long long *fidx = (long long *)smem;      // [C][D][2] lower/upper face index per axis
     double *cellv = (double *)(fidx + 2 * D * C);   // [C]: wiggle source
     int *blkflag = (int *)(cellv + C);
     T *X0 = (T *)(smem + ((C * (2 * D * sizeof(long long) + sizeof(double)) + sizeof(int) + 15) / 16) * 16);
-    T *X1 = X0 + C * cs_x;
-    T *G = X1 + C * cs_x;
+    T *X1 = X0 + Fx * CNP;
+    T *G = X1 + Fx * CNP;
     const Tab<T> &tb = TabSel<T>::get(P);
 
     // 1. load the tile's weights (and forcing coefficients); per-cell data
     const long long gbase = c0 * FNP, gend = NC * FNP;
     for (int i = tid; i < C * FNP; i += nt) {
         const int c = i / FNP, r = i - c * FNP;
+        const int f = r / NP, j = r - f * NP;
         long long gi = gbase + i;
         if (gi >= gend) gi = (NC - 1) * FNP + r;
-        X0[c * cs_x + r] = (T)a.cur[gi];
+        X0[f * CNP + c * NP + j] = (T)a.cur[gi];
     }
     if (forced) {
         for (int i = tid; i < C * D * NP; i += nt) {
             const int c = i / (D * NP), r = i - c * (D * NP);
+            const int f = r / NP, j = r - f * NP;
             long long cc = c0 + c;
             if (cc >= NC) cc = NC - 1;
-            X0[c * cs_x + FNP + r] = (T)a.forcing[cc * D * NP + r];
+            X0[(F + f) * CNP + c * NP + j] = (T)a.forcing[cc * D * NP + r];
         }
     }
     if (tid == 0) *blkflag = 0;
@@ -550,46 +621,35 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
     __syncthreads();
 
     // 2. point values of all fields: one operator pass per axis
-    if (forced) {
-        axis_pass<P, D, 0, T, M_B, false, F + D>(X0, cs_x, X1, cs_x, C);
+    line_pass<P, D, 0, T, M_B, false>(X0, X1, Fx * C);
+    __syncthreads();
+    line_pass<P, D, 1, T, M_B, false>(X1, X0, Fx * C);
+    __syncthreads();
+    if (D == 3) {
+        line_pass<P, D, (D == 3 ? 2 : 0), T, M_B, false>(X0, X1, Fx * C);
         __syncthreads();
-        axis_pass<P, D, 1, T, M_B, false, F + D>(X1, cs_x, X0, cs_x, C);
-        __syncthreads();
-        if (D == 3) {
-            axis_pass<P, D, (D == 3 ? 2 : 0), T, M_B, false, F + D>(X0, cs_x, X1, cs_x, C);
-            __syncthreads();
-        }
-    } else {
-        axis_pass<P, D, 0, T, M_B, false, F>(X0, cs_x, X1, cs_x, C);
-        __syncthreads();
-        axis_pass<P, D, 1, T, M_B, false, F>(X1, cs_x, X0, cs_x, C);
-        __syncthreads();
-        if (D == 3) {
-            axis_pass<P, D, (D == 3 ? 2 : 0), T, M_B, false, F>(X0, cs_x, X1, cs_x, C);
-            __syncthreads();
-        }
     }
     T *U = (D == 3) ? X1 : X0;
     T *Wk = (D == 3) ? X0 : X1;
 
     // 3. collocation gradients d/dxi of the stored fields
     if (GRAD) {
-        axis_pass<P, D, 0, T, M_D, false, F>(U, cs_x, G, cs_g, C);
-        axis_pass<P, D, 1, T, M_D, false, F>(U, cs_x, G + F * NP, cs_g, C);
-        if (D == 3) axis_pass<P, D, (D == 3 ? 2 : 0), T, M_D, false, F>(U, cs_x, G + 2 * F * NP, cs_g, C);
+        line_pass<P, D, 0, T, M_D, false>(U, G, F * C);
+        line_pass<P, D, 1, T, M_D, false>(U, G + F * CNP, F * C);
+        if (D == 3) line_pass<P, D, (D == 3 ? 2 : 0), T, M_D, false>(U, G + 2 * F * CNP, F * C);
         __syncthreads();
     }
 
     // 4. point fluxes (weighted by the volume Gauss weights) and sources
     const T gamma = (T)ph.gamma;
-    for (int q = tid; q < C * NP; q += nt) {
-        const int c = q / NP, j = q - c * NP;
+    for (int q = tid; q < CNP; q += nt) {
+        const int j = q % NP;                  // q = c * NP + j
         T u[F + D];
 #pragma unroll
-        for (int f = 0; f < F; ++f) u[f] = U[c * cs_x + f * NP + j];
+        for (int f = 0; f < F; ++f) u[f] = U[f * CNP + q];
         if (forced) {
 #pragma unroll
-            for (int i = 0; i < D; ++i) u[F + i] = U[c * cs_x + (F + i) * NP + j];
+            for (int i = 0; i < D; ++i) u[F + i] = U[(F + i) * CNP + q];
         }
         int jr = j;
         T wq = T(1);
@@ -604,7 +664,7 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
 #pragma unroll
             for (int b = 0; b < D; ++b)
 #pragma unroll
-                for (int f = 0; f < F; ++f) g[b][f] = G[c * cs_g + (b * F + f) * NP + j] * (T)ph.two_over_h;
+                for (int f = 0; f < F; ++f) g[b][f] = G[(b * F + f) * CNP + q] * (T)ph.two_over_h;
         }
         T eps = T(0), cs = T(0);
         if (PH == 2) {
@@ -626,7 +686,7 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
                 for (int f = 0; f < D + 2; ++f) fl[f] -= eps * g[b][f];
             }
 #pragma unroll
-            for (int f = 0; f < D + 2; ++f) G[c * cs_g + (b * F + f) * NP + j] = wq * fl[f];
+            for (int f = 0; f < D + 2; ++f) G[(b * F + f) * CNP + q] = wq * fl[f];
         }
         // sources, scaled to the common prefactor: Q = (h/2) w_j src
         const T hw = (T)ph.half_h * wq;
@@ -643,24 +703,24 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
             src[D + 1] = sv;
         }
 #pragma unroll
-        for (int f = 0; f < D + 2; ++f) U[c * cs_x + f * NP + j] = hw * src[f];
+        for (int f = 0; f < D + 2; ++f) U[f * CNP + q] = hw * src[f];
         if (PH == 2) {
             T div = T(0);
 #pragma unroll
             for (int i = 0; i < D; ++i) div += (g[i][1 + i] - s.v[i] * g[i][0]) * s.ir;
-            const T asrc = (T)ph.f_v * fmax(T(0), -div) + (T)cellv[c] - u[Fc] * cs * (T)ph.sink;
-            U[c * cs_x + Fc * NP + j] = hw * asrc;
+            const T asrc = (T)ph.f_v * fmax(T(0), -div) + (T)cellv[q / NP] - u[Fc] * cs * (T)ph.sink;
+            U[Fc * CNP + q] = hw * asrc;
         }
     }
     __syncthreads();
 
     // 5. Q += sum_a D_a^T (w f_a)
-    axis_pass<P, D, 0, T, M_DT, true, Fc>(G, cs_g, U, cs_x, C);
+    line_pass<P, D, 0, T, M_DT, true>(G, U, Fc * C);
     __syncthreads();
-    axis_pass<P, D, 1, T, M_DT, true, Fc>(G + F * NP, cs_g, U, cs_x, C);
+    line_pass<P, D, 1, T, M_DT, true>(G + F * CNP, U, Fc * C);
     __syncthreads();
     if (D == 3) {
-        axis_pass<P, D, (D == 3 ? 2 : 0), T, M_DT, true, Fc>(G + 2 * F * NP, cs_g, U, cs_x, C);
+        line_pass<P, D, (D == 3 ? 2 : 0), T, M_DT, true>(G + 2 * F * CNP, U, Fc * C);
         __syncthreads();
     }
 
@@ -677,7 +737,7 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
             const T Fl = fb[flo * (Fc * K) + f * K + k];
             const T Fu = fb[fhi * (Fc * K) + f * K + k];
             const int lo = k % S, hi = k / S;
-            T *po = U + c * cs_x + f * NP + lo + hi * S * P;
+            T *po = U + f * CNP + c * NP + lo + hi * S * P;
 #pragma unroll
             for (int i = 0; i < P; ++i) po[i * S] += tb.Lm[i] * Fl - tb.Lp[i] * Fu;
         }
@@ -685,12 +745,12 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
     }
 
     // 7. point -> modal projection of every stored field
-    axis_pass<P, D, 0, T, M_BT, false, F>(U, cs_x, Wk, cs_x, C);
+    line_pass<P, D, 0, T, M_BT, false>(U, Wk, F * C);
     __syncthreads();
-    axis_pass<P, D, 1, T, M_BT, false, F>(Wk, cs_x, U, cs_x, C);
+    line_pass<P, D, 1, T, M_BT, false>(Wk, U, F * C);
     __syncthreads();
     if (D == 3) {
-        axis_pass<P, D, (D == 3 ? 2 : 0), T, M_BT, false, F>(U, cs_x, Wk, cs_x, C);
+        line_pass<P, D, (D == 3 ? 2 : 0), T, M_BT, false>(U, Wk, F * C);
         __syncthreads();
     }
     const T *V = (D == 3) ? Wk : U;
@@ -701,9 +761,10 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
     int bad = 0;
     for (int i = tid; i < C * FNP; i += nt) {
         const int c = i / FNP, r = i - c * FNP;
+        const int f = r / NP, j = r - f * NP;
         const long long gi = gbase + i;
         if (gi >= gend) continue;
-        const double L = pref * (double)V[c * cs_x + r];
+        const double L = pref * (double)V[f * CNP + c * NP + j];
         const double cur = a.cur[gi];
         double o = a.c_cur * cur + a.c_L * dt * L;
         if (a.base) o += a.c_base * a.base[gi];
@@ -733,7 +794,7 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
             double Aa = 0.0, Tt = 0.0, ad = 0.0, td = 0.0;
             for (int m = 0; m < NP; ++m) {
                 const double x = wr[m];
-                const double xd = pref * (double)V[cl * cs_x + m];
+                const double xd = pref * (double)V[cl * NP + m];
                 Aa += x * x;
                 ad += x * xd;
                 bool tp = false;
@@ -762,6 +823,47 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
 }
 
 template <int D, int P, typename T, int PH>
+__global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    vol_body<D, P, T, PH>(ph, geo, a, smem, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Grouped volume/stage kernel over every box of one (dim, order) group.
+template <int D, int P, typename T, int PH>
+__global__ void __launch_bounds__(512) vol_kernel_batched(const BoxDesc *boxes, int nbox, StageDesc sd)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const long long b = xcd_block(blockIdx.x, gridDim.x);
+    const int i = owner_box(boxes, nbox, b, 0);
+    const BoxDesc &B = boxes[i];
+    const Phys ph = B.ph;
+    const Geo geo = B.geo;
+    VolArgs a;
+    a.cur = B.reg[sd.cur];
+    a.base = sd.base >= 0 ? B.reg[sd.base] : nullptr;
+    a.x2 = sd.x2 >= 0 ? B.reg[sd.x2] : nullptr;
+    a.out = B.reg[sd.out];
+    a.out2 = sd.out2 >= 0 ? B.reg[sd.out2] : nullptr;
+    a.c_base = sd.c_base;
+    a.c_cur = sd.c_cur;
+    a.c_L = sd.c_L;
+    a.d_x2 = sd.d_x2;
+    a.d_cur = sd.d_cur;
+    a.d_L = sd.d_L;
+    a.dt_ptr = B.dt;
+    a.dt = 0.0;
+    a.fb = B.fb;
+    a.forcing = nullptr;
+    a.R_prev = nullptr;
+    a.R_out = nullptr;
+    a.flag = B.flag;
+    a.check = 1;
+    a.cells_per_block = B.cells_per_block;
+    vol_body<D, P, T, PH>(ph, geo, a, smem, b - B.start[0]);
+}
+
+template <int D, int P, typename T, int PH>
 size_t vol_lds_bytes(int C, int Fx)
 {
     constexpr int NP = ipow(P, D);
@@ -777,16 +879,16 @@ size_t vol_lds_bytes(int C, int Fx)
 __device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
 template <int D, int P, int PH>
-__global__ void __launch_bounds__(512) cfl_kernel(Phys ph, Geo geo, CflArgs a)
+__device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const CflArgs &a, unsigned char *smem,
+                                         long long tile)
 {
     constexpr int NP = ipow(P, D);
     constexpr int Fc = D + 2;
     constexpr int FNP = Fld<D, PH>::F * NP;
-    extern __shared__ __align__(16) unsigned char smem[];
     const int C = a.cells_per_block;
     const int tid = threadIdx.x, nt = blockDim.x;
     const long long NC = geo.ncells;
-    const long long c0 = (long long)blockIdx.x * C;
+    const long long c0 = tile * C;
     double *X0 = (double *)smem;
     double *X1 = X0 + C * Fc * NP;
     double *red = X1 + C * Fc * NP;      // [2][nt]
@@ -831,9 +933,31 @@ __global__ void __launch_bounds__(512) cfl_kernel(Phys ph, Geo geo, CflArgs a)
         __syncthreads();
     }
     if (tid == 0) {
-        a.part[2 * blockIdx.x] = red[0];
-        a.part[2 * blockIdx.x + 1] = red[nt];
+        a.part[2 * tile] = red[0];
+        a.part[2 * tile + 1] = red[nt];
     }
+}
+
+template <int D, int P, int PH>
+__global__ void __launch_bounds__(512) cfl_kernel(Phys ph, Geo geo, CflArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    cfl_body<D, P, PH>(ph, geo, a, smem, blockIdx.x);
+}
+
+template <int D, int P, int PH>
+__global__ void __launch_bounds__(512) cfl_kernel_batched(const BoxDesc *boxes, int nbox)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const long long b = blockIdx.x;
+    const int i = owner_box(boxes, nbox, b, 2);
+    const Phys ph = boxes[i].ph;
+    const Geo geo = boxes[i].geo;
+    CflArgs a;
+    a.w = boxes[i].reg[0];
+    a.part = boxes[i].cfl_part;
+    a.cells_per_block = boxes[i].cfl_cells;
+    cfl_body<D, P, PH>(ph, geo, a, smem, b - boxes[i].start[2]);
 }
 
 template <int D, int P>

@@ -13,6 +13,9 @@ struct KernelSet {
     const void *vol;
     const void *face;
     const void *cfl;   // FP64 units only
+    const void *vol_b;     // grouped (batched ensemble) variants
+    const void *face_b;
+    const void *cfl_b;     // FP64 units only
     size_t (*vol_lds)(int C, int Fx);
     size_t (*face_lds)(int C);
     size_t (*cfl_lds)(int C, int nt);

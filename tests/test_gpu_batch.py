@@ -1,0 +1,81 @@
+"""GPU: batched ensemble (grouped launches replayed from a hipGraph) against
+per-box steps and the CPU oracle.  Bars: batched == per-box results bitwise
+(same kernels bodies, same per-box arithmetic); per-box dt and states against
+the oracle at 1e-14 / 1e-12 (state measure of oracle/compare.py)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle.compare import state_err
+from paper_2208_11131_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+dg = pytest.importorskip("paper_2208_11131_amd")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_batch_matches_per_box_and_oracle():
+    sides = [8, 16, 8, 12, 16, 8, 10]
+    orders = [2, 3, 4, 2, 6, 5, 3]
+    say("batch", sides, orders)
+    bt = dg.Batch(2, sides, orders, 5.0 / 3.0, cfl=0.5)
+    w0 = [W.ensemble_box(b, sides[b], orders[b]).numpy() for b in range(len(sides))]
+    wg = [torch.tensor(x, device="cuda") for x in w0]       # graph path
+    we = [torch.tensor(x, device="cuda") for x in w0]       # eager grouped path
+    for _ in range(3):
+        bt.step(wg, use_graph=True)
+    dts_g = bt.dts()
+    for _ in range(3):
+        bt.step(we, use_graph=False)
+    for i in range(len(sides)):
+        assert torch.equal(wg[i], we[i]), i
+        assert bt.box_check(i) == 0
+    # per-box launches on the same boxes
+    wp = [torch.tensor(x, device="cuda") for x in w0]
+    for i in range(len(sides)):
+        for _ in range(3):
+            bt.box_step_cfl(i, wp[i])
+        assert torch.equal(wg[i], wp[i]), i
+    # oracle: each box with its own CFL step
+    for i in range(len(sides)):
+        h = 1.0 / sides[i]
+        ref = O.Problem(2, (sides[i], sides[i]), h, orders[i], 5.0 / 3.0, cfl=0.5)
+        wr = w0[i]
+        for _ in range(3):
+            dt = ref.max_dt(wr)[0]
+            wr, _ = ref.step(wr, dt)
+        assert abs(dts_g[i] - dt) <= 1e-14 * dt
+        assert state_err(wg[i].cpu().numpy(), wr, 2) <= 1e-12, i
+
+
+def test_batch_graph_replays_after_pointer_change():
+    sides, orders = [8, 8], [3, 4]
+    say("batch pointers")
+    bt = dg.Batch(2, sides, orders, 5.0 / 3.0)
+    w0 = [W.ensemble_box(b, sides[b], orders[b]).numpy() for b in range(2)]
+    a = [torch.tensor(x, device="cuda") for x in w0]
+    c = [torch.tensor(x, device="cuda") for x in w0]
+    bt.step(a)
+    bt.step(a)
+    bt.step(c)          # new pointers: recapture
+    bt.step(c)
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert torch.equal(a[i], c[i])
+
+
+def test_batch_rejects_av_and_mixed_dims():
+    m2 = dg.make_mesh(2, (4, 4))
+    m3 = dg.make_mesh(3, (4, 4, 4))
+    with pytest.raises(dg.DgError):
+        dg.dg_batch_init([m2, m3], [2, 2], 1.4)
+    av = dg.dg_av_defaults()
+    with pytest.raises(dg.DgError):
+        dg.dg_batch_init([m2], [2], 1.4, av=av)
