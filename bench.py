@@ -139,6 +139,15 @@ def make_workload(name, order, device, precision):
     raise ValueError(name)
 
 
+def group_err(a, b, dim):
+    """max over density / momentum vector / energy of ||a - b||_inf / ||b||_inf."""
+    e = 0.0
+    for g in ([0], list(range(1, 1 + dim)), [dim + 1]):
+        den = np.abs(b[:, g]).max()
+        e = max(e, float(np.abs(a[:, g] - b[:, g]).max() / den))
+    return e
+
+
 def run_steps(s, w, n):
     for _ in range(n):
         s.step_cfl(w)
@@ -199,7 +208,7 @@ def measure(name, order, precision, steps, warmup, device="cuda"):
                        "algorithmic_bytes": by, "algorithmic_flops": fl}
         kern[k]["frac"] = kern[k]["achieved"] / kern[k]["peak"]
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    res = {"value": value, "ms": ms, "wall_s": wall, "stages": stages, "dofs": dofs, "desc": desc,
+    res = {"value": value, "ms": ms, "wall_s": wall, "stages": stages, "dofs": dofs, "desc": desc, "steps": steps + warmup,
            "kernels": kern, "dominant": dom, "cfl_ms": kt["cfl"][0], "solver": s, "state": w,
            "forcing": f}
     return res
@@ -289,6 +298,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the fp32_bulk and turbulence_3d records")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many bytes 3 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -298,6 +309,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8}))
+        return
     print("bench: %s p=%d %s, %d warmup + %d timed steps" % (args.config, args.order, args.precision, args.warmup,
                                                              args.steps), file=sys.stderr, flush=True)
     res = measure(args.config, args.order, args.precision, args.steps, args.warmup)
@@ -318,13 +338,21 @@ def main():
         "roofline": roof,
     }
     desc, stages, dofs = res["desc"], res["stages"], res["dofs"]
+    w64 = res["state"].cpu().numpy()
+    dim = 3 if desc["workload"].endswith("3d") else 2
     del res
     torch.cuda.empty_cache()
     if not args.no_extras:
         print("bench: fp32 bulk", file=sys.stderr, flush=True)
-        r32 = measure(args.config, args.order, "fp32", max(5, args.steps // 2), 2)
-        line["fp32_bulk"] = {"value": r32["value"], "ms_per_step": r32["ms"] / max(5, args.steps // 2),
-                             "speedup_vs_fp64": r32["value"] / line["value"]}
+        n32 = args.steps + args.warmup - 2
+        r32 = measure(args.config, args.order, "fp32", n32, 2)
+        # error of the FP32-bulk state against the FP64 state after the same
+        # number of CFL steps from the same initial state
+        err = group_err(r32["state"].cpu().numpy(), w64, dim)
+        line["fp32_bulk"] = {"value": r32["value"], "ms_per_step": r32["ms"] / n32,
+                             "speedup_vs_fp64": r32["value"] / line["value"],
+                             "state_err_vs_fp64": err, "after_steps": n32 + 2,
+                             "err_measure": "max over rho/momentum/energy of ||a-b||_inf/||b||_inf"}
         del r32
         torch.cuda.empty_cache()
         print("bench: 3D turbulence", file=sys.stderr, flush=True)

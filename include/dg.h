@@ -76,13 +76,17 @@ typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_BULK = 1 } dg_precision;
 
 /* Options (NULL = defaults): precision FP64; basis 0 = tensor set Q_n (the
  * only basis of this build); cfl = f_CFL of eq. timestep (default 0.5);
- * cells_per_block / faces_per_block: launch tiles, 0 = built-in table. */
+ * launch tiles (0 = built-in tuned table): cells per volume block, faces per
+ * face-kernel pencil, threads per volume / face block (multiples of 64,
+ * at most 512).  Results do not depend on the tiles. */
 typedef struct {
     int precision;
     int basis;
     double cfl;
     int cells_per_block;
     int faces_per_block;
+    int vol_threads;
+    int face_threads;
 } dg_options;
 
 void dg_av_defaults(dg_av_params *av);

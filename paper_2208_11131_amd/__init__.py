@@ -39,7 +39,8 @@ class dg_av_params(ctypes.Structure):
 
 class dg_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("basis", ctypes.c_int), ("cfl", ctypes.c_double),
-                ("cells_per_block", ctypes.c_int), ("faces_per_block", ctypes.c_int)]
+                ("cells_per_block", ctypes.c_int), ("faces_per_block", ctypes.c_int),
+                ("vol_threads", ctypes.c_int), ("face_threads", ctypes.c_int)]
 
 
 _V = ctypes.c_void_p
@@ -316,7 +317,8 @@ class Solver:
     ``precision``: "fp64" or "fp32" (FP32 bulk, FP64 state and RK)."""
 
     def __init__(self, dim, n, order, gamma, nu=0.0, kappa=0.0, lo=None, hi=None, bc=None, av=None,
-                 precision="fp64", cfl=0.5, cells_per_block=0, faces_per_block=0):
+                 precision="fp64", cfl=0.5, cells_per_block=0, faces_per_block=0, vol_threads=0,
+                 face_threads=0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the DG library runs on the GPU only")
         self.dim, self.order = dim, order
@@ -334,6 +336,8 @@ class Solver:
         opt.cfl = cfl
         opt.cells_per_block = cells_per_block
         opt.faces_per_block = faces_per_block
+        opt.vol_threads = vol_threads
+        opt.face_threads = face_threads
         self.ctx = dg_init(self.mesh, order, gamma, nu, kappa, avp, opt)
         self.nfields = dg_num_fields(self.ctx)
         self.ncells = 1

@@ -321,6 +321,22 @@ __global__ void totals_final(const double *part, int nblk, int Fc, double *out)
 
 int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
+struct TileEntry {
+    int dim, order, prec, phys, forced, vol_C, vol_T, face_C, face_T;
+};
+
+const TileEntry kTiles[] = {
+#include "dg_tiles.inc"
+    {0, 0, 0, 0, 0, 0, 0, 0, 0}};
+
+// Tuned tiles for this (dim, order, precision, physics, forcing), if any.
+const TileEntry *find_tiles(int dim, int order, int prec, int phys, int forced)
+{
+    for (const TileEntry &t : kTiles)
+        if (t.dim == dim && t.order == order && t.prec == prec && t.phys == phys && t.forced == forced) return &t;
+    return nullptr;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -553,6 +569,8 @@ void dg_options_defaults(dg_options *opt)
     opt->cfl = 0.5;
     opt->cells_per_block = 0;
     opt->faces_per_block = 0;
+    opt->vol_threads = 0;
+    opt->face_threads = 0;
 }
 
 const char *dg_status_str(dg_status s)
@@ -583,6 +601,9 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     if (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_BULK) return DG_EINVAL;
     if (o.basis != 0) return DG_EUNSUPPORTED;
     if (!(o.cfl > 0.0) || o.cells_per_block < 0 || o.faces_per_block < 0) return DG_EINVAL;
+    if (o.vol_threads < 0 || o.vol_threads > 512 || o.vol_threads % 64 || o.face_threads < 0 ||
+        o.face_threads > 512 || o.face_threads % 64)
+        return DG_EINVAL;
     const int d = mesh->dim;
     double h = 0.0;
     for (int a = 0; a < d; ++a) {
@@ -673,14 +694,23 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         return DG_EUNSUPPORTED;
     }
 
-    // launch tiles: about 256 volume points / 128 face points per block
+    // launch tiles: explicit options, else the tuned table, else about 256
+    // volume points / 128 face points per block
     const int Fx = c->F + d;
+    const TileEntry *te = find_tiles(d, order, c->precision, c->phys, 0);
     if (o.cells_per_block > 0)
         c->vol_C = o.cells_per_block;
+    else if (te)
+        c->vol_C = te->vol_C;
     else
         c->vol_C = std::max(1, 256 / c->NP);
     while (c->vol_C > 1 && c->ks.vol_lds(c->vol_C, Fx) > LDS_MAX) --c->vol_C;
-    c->vol_T = std::min(512, std::max(64, roundup(c->vol_C * c->NP, 64)));
+    if (o.vol_threads > 0)
+        c->vol_T = o.vol_threads;
+    else if (te && o.cells_per_block == 0)
+        c->vol_T = te->vol_T;
+    else
+        c->vol_T = std::min(512, std::max(64, roundup(c->vol_C * c->NP, 64)));
     c->vol_lds = c->ks.vol_lds(c->vol_C, c->F);
     c->vol_lds_forced = c->ks.vol_lds(c->vol_C, Fx);
     if (c->vol_lds > LDS_MAX) {
@@ -689,10 +719,17 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     }
     if (o.faces_per_block > 0)
         c->face_C = o.faces_per_block;
+    else if (te)
+        c->face_C = te->face_C;
     else
         c->face_C = std::max(1, 128 / c->K);
     while (c->face_C > 1 && c->ks.face_lds(c->face_C) > 64 * 1024) --c->face_C;
-    c->face_T = std::min(512, std::max(64, roundup(c->face_C * c->K, 64)));
+    if (o.face_threads > 0)
+        c->face_T = o.face_threads;
+    else if (te && o.faces_per_block == 0)
+        c->face_T = te->face_T;
+    else
+        c->face_T = std::min(512, std::max(64, roundup(c->face_C * c->K, 64)));
     c->face_lds = c->ks.face_lds(c->face_C);
     c->cfl_C = std::max(1, 256 / c->NP);
     c->cfl_T = 256;

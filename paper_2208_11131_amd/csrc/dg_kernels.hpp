@@ -112,6 +112,81 @@ __device__ __forceinline__ void line_pass(const T *__restrict__ in, T *__restric
     }
 }
 
+// Padded point layout of one per-cell array: rows along x hold PP entries
+// (PP = p + 1 for even p, p for odd p), so that the lines of a pass along any
+// axis fall into different LDS banks.  Point j = j_x + p (j_y + p j_z) lives
+// at j_x + PP (j_y + p j_z); an array takes NAP = PP p^(d-1) entries.
+template <int P>
+struct Pad {
+    static constexpr int PP = (P % 2 == 0) ? P + 1 : P;
+};
+
+template <int P>
+__device__ __forceinline__ int ppos(int j)
+{
+    return (j % P) + Pad<P>::PP * (j / P);
+}
+
+// line_pass over narr contiguous padded arrays of (d-dimensional) points.
+// Each thread takes two lines per iteration (q and q + blockDim) and issues
+// the loads of both before their FMAs, so that two LDS round trips overlap.
+template <int P, int DA, int AX>
+__device__ __forceinline__ int pad_line_offset(int q)
+{
+    constexpr int PP = Pad<P>::PP;
+    constexpr int NAP = PP * ipow(P, DA - 1);
+    if (AX == 0) return q * PP;
+    if (AX == 1) return (q / P) * (PP * P) + (q % P);
+    const int a = q / (P * P), t = q - a * (P * P);
+    return a * NAP + (t % P) + PP * (t / P);
+}
+
+template <int P, int DA, int AX, typename T, int MAT, bool ACC>
+__device__ __forceinline__ void line_pass_pad(const T *__restrict__ in, T *__restrict__ out, int narr)
+{
+    constexpr int PP = Pad<P>::PP;
+    constexpr int NL = ipow(P, DA - 1);                  // lines per array
+    constexpr int S = (AX == 0) ? 1 : (AX == 1 ? PP : PP * P);
+    const int nitems = narr * NL;
+    const int nt = blockDim.x;
+    for (int q = threadIdx.x; q < nitems; q += 2 * nt) {
+        const bool two = q + nt < nitems;
+        const int o0 = pad_line_offset<P, DA, AX>(q);
+        const int o1 = two ? pad_line_offset<P, DA, AX>(q + nt) : o0;
+        T x0[P], x1[P], y0[P], y1[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            x0[k] = in[o0 + k * S];
+            x1[k] = in[o1 + k * S];
+        }
+        if (ACC) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                y0[i] = out[o0 + i * S];
+                y1[i] = out[o1 + i * S];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            T a0 = ACC ? y0[i] : T(0), a1 = ACC ? y1[i] : T(0);
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const T m = mat<P, T, MAT>(k, i);
+                a0 = fma(m, x0[k], a0);
+                a1 = fma(m, x1[k], a1);
+            }
+            y0[i] = a0;
+            y1[i] = a1;
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) out[o0 + i * S] = y0[i];
+        if (two) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) out[o1 + i * S] = y1[i];
+        }
+    }
+}
+
 // Fields per physics variant: PH = 0 Euler, 1 Navier-Stokes, 2 artificial
 // viscosity (alpha field; Navier-Stokes terms switched at run time).
 template <int D, int PH>
@@ -202,34 +277,55 @@ __device__ __forceinline__ void hllc(const T *uL, const T *uR, int a, T gamma, T
     for (int k = 0; k < D + 2; ++k) F[k] += S * (us[k] - u[k]);
 }
 
-// Navier-Stokes flux along axis a (added with a minus sign to the Euler flux):
-// (0, Pi_{.a}, v.Pi_{.a} + chi (gamma-1) rho d_a e_int),
-// Pi = nu rho (grad v + grad v^T - 2/3 div v I).  g[b][f]: d u_f / d x_b.
+// Navier-Stokes flux (added with a minus sign to the Euler flux), Sec. 3.3:
+// along axis a, (0, Pi_{.a}, v.Pi_{.a} + chi (gamma-1) rho d_a e_int) with
+// Pi = nu rho (grad v + grad v^T - 2/3 div v I) and primitive gradients from
+// conserved ones.  g[b][f] = d u_f / d x_b.  The velocity-gradient tensor,
+// its divergence and grad e_int are formed once per point (NsGrad) and
+// shared by every direction.
 template <int D, typename T>
-__device__ __forceinline__ void ns_flux(const T *u, const Prim<D, T> &s, const T (*g)[MAXF], int a, T gamma, T nu,
-                                        T chi, T *fv)
+struct NsGrad {
+    T dv[D][D];   // dv[i][b] = d v_i / d x_b
+    T div;
+    T de[D];      // d e_int / d x_b
+};
+
+template <int D, typename T>
+__device__ __forceinline__ NsGrad<D, T> ns_grad(const T *u, const Prim<D, T> &s, const T (*g)[MAXF])
 {
-    T dv[D][D];
+    NsGrad<D, T> n;
 #pragma unroll
     for (int b = 0; b < D; ++b)
 #pragma unroll
-        for (int i = 0; i < D; ++i) dv[i][b] = (g[b][1 + i] - s.v[i] * g[b][0]) * s.ir;
-    T div = T(0);
+        for (int i = 0; i < D; ++i) n.dv[i][b] = (g[b][1 + i] - s.v[i] * g[b][0]) * s.ir;
+    n.div = T(0);
 #pragma unroll
-    for (int i = 0; i < D; ++i) div += dv[i][i];
-    T de = (g[a][D + 1] - u[D + 1] * s.ir * g[a][0]) * s.ir;
+    for (int i = 0; i < D; ++i) n.div += n.dv[i][i];
+    const T eps = u[D + 1] * s.ir;
 #pragma unroll
-    for (int i = 0; i < D; ++i) de -= s.v[i] * dv[i][a];
+    for (int b = 0; b < D; ++b) {
+        T de = (g[b][D + 1] - eps * g[b][0]) * s.ir;
+#pragma unroll
+        for (int i = 0; i < D; ++i) de -= s.v[i] * n.dv[i][b];
+        n.de[b] = de;
+    }
+    return n;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void ns_flux(const Prim<D, T> &s, const NsGrad<D, T> &n, int a, T gamma, T nu, T chi,
+                                        T *fv)
+{
     const T nr = nu * s.rho;
     fv[0] = T(0);
     T vp = T(0);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        const T pi = nr * (dv[i][a] + dv[a][i] - (i == a ? T(2.0 / 3.0) * div : T(0)));
+        const T pi = nr * (n.dv[i][a] + n.dv[a][i] - (i == a ? T(2.0 / 3.0) * n.div : T(0)));
         fv[1 + i] = pi;
         vp += s.v[i] * pi;
     }
-    fv[D + 1] = vp + chi * (gamma - T(1)) * s.rho * de;
+    fv[D + 1] = vp + chi * (gamma - T(1)) * s.rho * n.de[a];
 }
 
 template <typename T>
@@ -258,9 +354,13 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     constexpr int FNP = F * NP;
     constexpr int NA = GRAD ? 4 : 2;
     constexpr int S = ipow(P, AX);
+    constexpr int PP = Pad<P>::PP;
+    constexpr int NAP = PP * NP / P;                      // padded cell array
+    constexpr int NAF = (D == 3) ? PP * P : PP;           // padded face array
+    constexpr int SP = (AX == 0) ? 1 : (AX == 1 ? PP : PP * P);   // padded stride along AX
     const int C = a.faces_per_block;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int Q = C * F * K;
+    const int Q = C * F * NAF;
     const int na = geo.n[AX], nfa = geo.nf[AX];
     const int npl = (nfa + C - 1) / C;
     const long long line = pen_id / npl;
@@ -279,9 +379,11 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
 
     long long *cellidx = (long long *)smem;               // [C+1]
     int *mir = (int *)(cellidx + (C + 1));                // [C+1]
-    T *W = (T *)(smem + (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16);   // [C+1][F][NP]
-    T *A = W + (C + 1) * FNP;                             // [NA][C][F][K]
-    T *Sx = ((C + 1) * FNP >= 5 * Q) ? W : (A + NA * Q);  // scratch [5][C][F][K]
+    // LDS: cell coefficients W, overlaid after the contraction by the scratch
+    // Sx (5 Q entries), then the contraction results A (NA Q entries)
+    T *W = (T *)(smem + (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16);   // [C+1][F][NAP]
+    T *Sx = W;                                            // scratch [5][C][F][NAF]
+    T *A = W + max((C + 1) * F * NAP, 5 * Q);             // [NA][C][F][NAF]
 
     for (int s = tid; s <= C; s += nt) {
         int ca = a0 + s - 1;
@@ -303,11 +405,26 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         mir[s] = m;
     }
     __syncthreads();
-    for (int i = tid; i < (C + 1) * FNP; i += nt) {
-        const int s = i / FNP, e = i - s * FNP;
-        double v = a.w[cellidx[s] * FNP + e];
-        if (mir[s] && (((e % NP) / S) % P) & 1) v = -v;
-        W[i] = (T)v;
+    constexpr int UNR = 4;      // loads in flight per thread
+    for (int i0 = tid; i0 < (C + 1) * FNP; i0 += UNR * nt) {
+        double v[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int i = i0 + u * nt;
+            const int sl = i < (C + 1) * FNP ? i / FNP : 0;
+            v[u] = i < (C + 1) * FNP ? a.w[cellidx[sl] * FNP + (i - sl * FNP)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int i = i0 + u * nt;
+            if (i < (C + 1) * FNP) {
+                const int sl = i / FNP, e = i - sl * FNP;
+                const int f = e / NP, j = e - f * NP;
+                double x = v[u];
+                if (mir[sl] && ((j / S) % P) & 1) x = -x;
+                W[(sl * F + f) * NAP + ppos<P>(j)] = (T)x;
+            }
+        }
     }
     __syncthreads();
 
@@ -319,13 +436,13 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
             const int t = q - cf * K;
             const int c = cf / F, f = cf - c * F;
             const int lo = t % S, hi = t / S;
-            const int offL = c * FNP + f * NP + lo + hi * S * P;
-            const int offR = offL + FNP;
+            const int offL = (c * F + f) * NAP + ppos<P>(lo + hi * S * P);
+            const int offR = offL + F * NAP;
             T xl[P], xr[P];
 #pragma unroll
             for (int m = 0; m < P; ++m) {
-                xl[m] = W[offL + m * S];
-                xr[m] = W[offR + m * S];
+                xl[m] = W[offL + m * SP];
+                xr[m] = W[offR + m * SP];
             }
             T tl = T(0), tr = T(0);
 #pragma unroll
@@ -333,8 +450,9 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                 tl = fma(tb.ep[m], xl[m], tl);
                 tr = fma(tb.em[m], xr[m], tr);
             }
-            A[0 * Q + q] = tl;
-            A[1 * Q + q] = tr;
+            const int qa = cf * NAF + ppos<P>(t);
+            A[0 * Q + qa] = tl;
+            A[1 * Q + qa] = tr;
             if (GRAD) {
                 T rv = T(0), rn = T(0);
 #pragma unroll
@@ -344,8 +462,8 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                     rn = fma(tb.rdL[m], xl[m], rn);
                     rn = fma(tb.rdR[m], xr[m], rn);
                 }
-                A[2 * Q + q] = rv;
-                A[3 * Q + q] = rn;
+                A[2 * Q + qa] = rv;
+                A[3 * Q + qa] = rn;
             }
         }
     }
@@ -354,8 +472,8 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     // transverse transforms to the face Gauss points
     const T *tLp, *tRp, *utp = nullptr, *rnp = nullptr, *d1p = nullptr, *d2p = nullptr;
     if (D == 2) {
-        axis_pass<P, 1, 0, T, M_B, false, 1>(A, K, Sx, K, NA * C * F);
-        if (GRAD) axis_pass<P, 1, 0, T, M_BD, false, 1>(A + 2 * Q, K, Sx + 4 * Q, K, C * F);
+        line_pass_pad<P, 1, 0, T, M_B, false>(A, Sx, NA * C * F);
+        if (GRAD) line_pass_pad<P, 1, 0, T, M_BD, false>(A + 2 * Q, Sx + 4 * Q, C * F);
         __syncthreads();
         tLp = Sx;
         tRp = Sx + Q;
@@ -364,14 +482,14 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         d1p = Sx + 4 * Q;
     } else {
         // (t1, t2) = transverse axes of the face in ascending order
-        axis_pass<P, 2, 0, T, M_B, false, 1>(A, K, Sx, K, NA * C * F);
-        if (GRAD) axis_pass<P, 2, 0, T, M_BD, false, 1>(A + 2 * Q, K, Sx + 4 * Q, K, C * F);
+        line_pass_pad<P, 2, 0, T, M_B, false>(A, Sx, NA * C * F);
+        if (GRAD) line_pass_pad<P, 2, 0, T, M_BD, false>(A + 2 * Q, Sx + 4 * Q, C * F);
         __syncthreads();
-        axis_pass<P, 2, 1, T, M_B, false, 1>(Sx, K, A, K, NA * C * F);
+        line_pass_pad<P, 2, 1, T, M_B, false>(Sx, A, NA * C * F);
         __syncthreads();
         if (GRAD) {
-            axis_pass<P, 2, 1, T, M_BD, false, 1>(Sx + 2 * Q, K, Sx, K, C * F);
-            axis_pass<P, 2, 1, T, M_B, false, 1>(Sx + 4 * Q, K, Sx + Q, K, C * F);
+            line_pass_pad<P, 2, 1, T, M_BD, false>(Sx + 2 * Q, Sx, C * F);
+            line_pass_pad<P, 2, 1, T, M_B, false>(Sx + 4 * Q, Sx + Q, C * F);
             __syncthreads();
         }
         tLp = A;
@@ -389,11 +507,12 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     for (int q = tid; q < C * K; q += nt) {
         const int c = q / K, k = q - c * K;
         if (c >= nface) continue;
+        const int kp = ppos<P>(k);
         T uL[D + 2], uR[D + 2], Fh[D + 2];
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) {
-            uL[f] = tLp[(c * F + f) * K + k];
-            uR[f] = tRp[(c * F + f) * K + k];
+            uL[f] = tLp[(c * F + f) * NAF + kp];
+            uR[f] = tRp[(c * F + f) * NAF + kp];
         }
         hllc<D, T>(uL, uR, AX, gamma, Fh);
         if (GRAD) {
@@ -403,7 +522,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
             constexpr int T2 = (D == 3) ? ((AX == 2) ? 1 : 2) : 0;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                const int idx = (c * F + f) * K + k;
+                const int idx = (c * F + f) * NAF + kp;
                 ut[f] = utp[idx];
                 g[AX][f] = rnp[idx] * (T)ph.inv_fh;
                 g[T1][f] = d1p[idx] * (T)ph.two_over_h;
@@ -412,7 +531,8 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
             const Prim<D, T> s = primitives<D, T>(ut, gamma);
             if (PH == 1 || ph.ns_on) {
                 T fv[D + 2];
-                ns_flux<D, T>(ut, s, g, AX, gamma, (T)ph.nu, (T)ph.kappa, fv);
+                const NsGrad<D, T> ng = ns_grad<D, T>(ut, s, g);
+                ns_flux<D, T>(s, ng, AX, gamma, (T)ph.nu, (T)ph.kappa, fv);
 #pragma unroll
                 for (int f = 0; f < D + 2; ++f) Fh[f] -= fv[f];
             }
@@ -483,8 +603,8 @@ __global__ void __launch_bounds__(512) face_kernel_batched(const BoxDesc *boxes,
     extern __shared__ __align__(16) unsigned char smem[];
     const long long b = xcd_block(blockIdx.x, gridDim.x);
     const int i = owner_box(boxes, nbox, b, 1);
-    const Phys ph = boxes[i].ph;
-    const Geo geo = boxes[i].geo;
+    const Phys &ph = boxes[i].ph;
+    const Geo &geo = boxes[i].geo;
     FaceArgs a;
     a.w = boxes[i].reg[stage_cur];
     a.fb = boxes[i].fb;
@@ -501,20 +621,21 @@ __global__ void __launch_bounds__(512) face_kernel_batched(const BoxDesc *boxes,
 }
 
 // LDS bytes of the face kernel for pencils of C faces: slot indices, the C+1
-// cells' coefficients W, the contraction results A (NA C F p^(d-1)) and a
-// scratch of 5 C F p^(d-1) that overlays W when W is large enough (W is dead
-// after the normal contraction).
+// cells' coefficients W overlaid by a scratch of 5 C F p^(d-1) (W is dead
+// after the normal contraction), and the contraction results A (NA C F
+// p^(d-1)).
 template <int D, int P, typename T, int PH>
 size_t face_lds_bytes(int C)
 {
     constexpr int NP = ipow(P, D);
     constexpr int K = NP / P;
     constexpr int F = Fld<D, PH>::F;
+    constexpr int PP = Pad<P>::PP;
     const size_t hdr = (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16;
-    const size_t Q = (size_t)C * F * K;
-    const size_t W = (size_t)(C + 1) * F * NP;
+    const size_t Q = (size_t)C * F * (PP * K / P);
+    const size_t W = (size_t)(C + 1) * F * (PP * NP / P);
     const size_t NA = Fld<D, PH>::GRAD ? 4 : 2;
-    const size_t tot = W + NA * Q + (W >= 5 * Q ? 0 : 5 * Q);
+    const size_t tot = (W > 5 * Q ? W : 5 * Q) + NA * Q;
     return hdr + sizeof(T) * tot;
 }
 
@@ -535,12 +656,14 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     const bool forced = a.forcing != nullptr;
     const int Fx = F + (forced ? D : 0);
     const int C = a.cells_per_block;
-    const int CNP = C * NP;                   // one field of the tile
+    constexpr int NAP = Pad<P>::PP * NP / P;  // padded per-cell array
+    const int CNP = C * NAP;                  // one field of the tile
     const int tid = threadIdx.x, nt = blockDim.x;
     const long long NC = geo.ncells;
     const long long c0 = tile * C;
 
     // LDS, field-major: X0/X1 [field][cell][point], G [axis][field][cell][point]
+    // (points in the padded layout of Pad<P>)
     long long *fidx = (long long *)smem;      // [C][D][2] lower/upper face index per axis
     double *cellv = (double *)(fidx + 2 * D * C);   // [C]: wiggle source
     int *blkflag = (int *)(cellv + C);
@@ -549,22 +672,49 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     T *G = X1 + Fx * CNP;
     const Tab<T> &tb = TabSel<T>::get(P);
 
-    // 1. load the tile's weights (and forcing coefficients); per-cell data
+    // 1. load the tile's weights (and forcing coefficients); per-cell data.
+    //    UNR loads per thread are issued before their LDS stores.
+    constexpr int UNR = 4;
     const long long gbase = c0 * FNP, gend = NC * FNP;
-    for (int i = tid; i < C * FNP; i += nt) {
-        const int c = i / FNP, r = i - c * FNP;
-        const int f = r / NP, j = r - f * NP;
-        long long gi = gbase + i;
-        if (gi >= gend) gi = (NC - 1) * FNP + r;
-        X0[f * CNP + c * NP + j] = (T)a.cur[gi];
+    for (int i0 = tid; i0 < C * FNP; i0 += UNR * nt) {
+        double v[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int i = i0 + u * nt;
+            long long gi = gbase + i;
+            if (gi >= gend) gi = (NC - 1) * FNP + i % FNP;
+            v[u] = (i < C * FNP) ? a.cur[gi] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int i = i0 + u * nt;
+            if (i < C * FNP) {
+                const int c = i / FNP, r = i - c * FNP;
+                const int f = r / NP, j = r - f * NP;
+                X0[f * CNP + c * NAP + ppos<P>(j)] = (T)v[u];
+            }
+        }
     }
     if (forced) {
-        for (int i = tid; i < C * D * NP; i += nt) {
-            const int c = i / (D * NP), r = i - c * (D * NP);
-            const int f = r / NP, j = r - f * NP;
-            long long cc = c0 + c;
-            if (cc >= NC) cc = NC - 1;
-            X0[(F + f) * CNP + c * NP + j] = (T)a.forcing[cc * D * NP + r];
+        for (int i0 = tid; i0 < C * D * NP; i0 += UNR * nt) {
+            double v[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int i = i0 + u * nt;
+                const int c = i / (D * NP), r = i - c * (D * NP);
+                long long cc = c0 + c;
+                if (cc >= NC) cc = NC - 1;
+                v[u] = (i < C * D * NP) ? a.forcing[cc * D * NP + r] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int i = i0 + u * nt;
+                if (i < C * D * NP) {
+                    const int c = i / (D * NP), r = i - c * (D * NP);
+                    const int f = r / NP, j = r - f * NP;
+                    X0[(F + f) * CNP + c * NAP + ppos<P>(j)] = (T)v[u];
+                }
+            }
         }
     }
     if (tid == 0) *blkflag = 0;
@@ -621,12 +771,12 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     __syncthreads();
 
     // 2. point values of all fields: one operator pass per axis
-    line_pass<P, D, 0, T, M_B, false>(X0, X1, Fx * C);
+    line_pass_pad<P, D, 0, T, M_B, false>(X0, X1, Fx * C);
     __syncthreads();
-    line_pass<P, D, 1, T, M_B, false>(X1, X0, Fx * C);
+    line_pass_pad<P, D, 1, T, M_B, false>(X1, X0, Fx * C);
     __syncthreads();
     if (D == 3) {
-        line_pass<P, D, (D == 3 ? 2 : 0), T, M_B, false>(X0, X1, Fx * C);
+        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_B, false>(X0, X1, Fx * C);
         __syncthreads();
     }
     T *U = (D == 3) ? X1 : X0;
@@ -634,16 +784,17 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
 
     // 3. collocation gradients d/dxi of the stored fields
     if (GRAD) {
-        line_pass<P, D, 0, T, M_D, false>(U, G, F * C);
-        line_pass<P, D, 1, T, M_D, false>(U, G + F * CNP, F * C);
-        if (D == 3) line_pass<P, D, (D == 3 ? 2 : 0), T, M_D, false>(U, G + 2 * F * CNP, F * C);
+        line_pass_pad<P, D, 0, T, M_D, false>(U, G, F * C);
+        line_pass_pad<P, D, 1, T, M_D, false>(U, G + F * CNP, F * C);
+        if (D == 3) line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_D, false>(U, G + 2 * F * CNP, F * C);
         __syncthreads();
     }
 
     // 4. point fluxes (weighted by the volume Gauss weights) and sources
     const T gamma = (T)ph.gamma;
-    for (int q = tid; q < CNP; q += nt) {
-        const int j = q % NP;                  // q = c * NP + j
+    for (int qq = tid; qq < C * NP; qq += nt) {
+        const int cq = qq / NP, j = qq - cq * NP;
+        const int q = cq * NAP + ppos<P>(j);   // padded position of point j of cell cq
         T u[F + D];
 #pragma unroll
         for (int f = 0; f < F; ++f) u[f] = U[f * CNP + q];
@@ -671,13 +822,15 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
             cs = sqrt(gamma * s.p * s.ir);
             eps = (T)ph.av_scale * clamp_alpha(u[Fc], (T)ph.alpha_max) * cs * (T)ph.eps_fac;
         }
+        NsGrad<D, T> ng;
+        if (GRAD) ng = ns_grad<D, T>(u, s, g);
 #pragma unroll
         for (int b = 0; b < D; ++b) {
             T fl[D + 2];
             euler_flux<D, T>(u, s, b, fl);
             if (PH == 1 || (PH == 2 && ph.ns_on)) {
                 T fv[D + 2];
-                ns_flux<D, T>(u, s, g, b, gamma, (T)ph.nu, (T)ph.kappa, fv);
+                ns_flux<D, T>(s, ng, b, gamma, (T)ph.nu, (T)ph.kappa, fv);
 #pragma unroll
                 for (int f = 0; f < D + 2; ++f) fl[f] -= fv[f];
             }
@@ -705,52 +858,64 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) U[f * CNP + q] = hw * src[f];
         if (PH == 2) {
-            T div = T(0);
-#pragma unroll
-            for (int i = 0; i < D; ++i) div += (g[i][1 + i] - s.v[i] * g[i][0]) * s.ir;
-            const T asrc = (T)ph.f_v * fmax(T(0), -div) + (T)cellv[q / NP] - u[Fc] * cs * (T)ph.sink;
+            const T asrc = (T)ph.f_v * fmax(T(0), -ng.div) + (T)cellv[cq] - u[Fc] * cs * (T)ph.sink;
             U[Fc * CNP + q] = hw * asrc;
         }
     }
     __syncthreads();
 
     // 5. Q += sum_a D_a^T (w f_a)
-    line_pass<P, D, 0, T, M_DT, true>(G, U, Fc * C);
+    line_pass_pad<P, D, 0, T, M_DT, true>(G, U, Fc * C);
     __syncthreads();
-    line_pass<P, D, 1, T, M_DT, true>(G + F * CNP, U, Fc * C);
+    line_pass_pad<P, D, 1, T, M_DT, true>(G + F * CNP, U, Fc * C);
     __syncthreads();
     if (D == 3) {
-        line_pass<P, D, (D == 3 ? 2 : 0), T, M_DT, true>(G + 2 * F * CNP, U, Fc * C);
+        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_DT, true>(G + 2 * F * CNP, U, Fc * C);
         __syncthreads();
     }
 
-    // 6. surface lift in point space: Q(i, k) += L_i(-1) F_lower(k) - L_i(+1) F_upper(k)
-#pragma unroll
-    for (int ax = 0; ax < D; ++ax) {
-        const int S = (ax == 0) ? 1 : (ax == 1 ? P : P * P);
-        const T *fb = (const T *)a.fb + geo.fb_off[ax];
-        for (int q = tid; q < C * Fc * K; q += nt) {
-            const int c = q / (Fc * K);
+    // 6. surface lift in point space: Q(i, k) += L_i(-1) F_lower(k) - L_i(+1) F_upper(k).
+    //    Each round first loads the face fluxes of every axis, then applies
+    //    them axis by axis (a barrier between axes: their lines intersect).
+    {
+        const int nlift = C * Fc * K;
+        const int rounds = (nlift + nt - 1) / nt;          // uniform over the block
+        for (int rr = 0; rr < rounds; ++rr) {
+            const int q = tid + rr * nt;
+            const bool act = q < nlift;
+            const int c = act ? q / (Fc * K) : 0;
             const int r = q - c * (Fc * K);
-            const int f = r / K, k = r - f * K;
-            const long long flo = fidx[(c * D + ax) * 2], fhi = fidx[(c * D + ax) * 2 + 1];
-            const T Fl = fb[flo * (Fc * K) + f * K + k];
-            const T Fu = fb[fhi * (Fc * K) + f * K + k];
-            const int lo = k % S, hi = k / S;
-            T *po = U + f * CNP + c * NP + lo + hi * S * P;
+            const int f = act ? r / K : 0, k = act ? r - f * K : 0;
+            T Fl[D], Fu[D];
 #pragma unroll
-            for (int i = 0; i < P; ++i) po[i * S] += tb.Lm[i] * Fl - tb.Lp[i] * Fu;
+            for (int ax = 0; ax < D; ++ax) {
+                const T *fb = (const T *)a.fb + geo.fb_off[ax];
+                const long long flo = fidx[(c * D + ax) * 2], fhi = fidx[(c * D + ax) * 2 + 1];
+                Fl[ax] = act ? fb[flo * (Fc * K) + f * K + k] : T(0);
+                Fu[ax] = act ? fb[fhi * (Fc * K) + f * K + k] : T(0);
+            }
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                const int S = (ax == 0) ? 1 : (ax == 1 ? P : P * P);
+                if (act) {
+                    const int lo = k % S, hi = k / S;
+                    T *po = U + f * CNP + c * NAP;
+                    const int j0 = lo + hi * S * P;
+#pragma unroll
+                    for (int i = 0; i < P; ++i) po[ppos<P>(j0 + i * S)] += tb.Lm[i] * Fl[ax] - tb.Lp[i] * Fu[ax];
+                }
+                __syncthreads();
+            }
         }
-        __syncthreads();
     }
 
     // 7. point -> modal projection of every stored field
-    line_pass<P, D, 0, T, M_BT, false>(U, Wk, F * C);
+    line_pass_pad<P, D, 0, T, M_BT, false>(U, Wk, F * C);
     __syncthreads();
-    line_pass<P, D, 1, T, M_BT, false>(Wk, U, F * C);
+    line_pass_pad<P, D, 1, T, M_BT, false>(Wk, U, F * C);
     __syncthreads();
     if (D == 3) {
-        line_pass<P, D, (D == 3 ? 2 : 0), T, M_BT, false>(U, Wk, F * C);
+        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_BT, false>(U, Wk, F * C);
         __syncthreads();
     }
     const T *V = (D == 3) ? Wk : U;
@@ -759,22 +924,30 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
     const double pref = ph.pref;
     int bad = 0;
-    for (int i = tid; i < C * FNP; i += nt) {
-        const int c = i / FNP, r = i - c * FNP;
-        const int f = r / NP, j = r - f * NP;
-        const long long gi = gbase + i;
-        if (gi >= gend) continue;
-        const double L = pref * (double)V[f * CNP + c * NP + j];
-        const double cur = a.cur[gi];
-        double o = a.c_cur * cur + a.c_L * dt * L;
-        if (a.base) o += a.c_base * a.base[gi];
-        if (a.out2) {
-            double o2 = a.d_cur * cur + a.d_L * dt * L;
-            if (a.x2) o2 += a.d_x2 * a.x2[gi];
-            a.out2[gi] = o2;
+    for (int i0 = tid; i0 < C * FNP; i0 += UNR * nt) {
+        double cu[UNR], ba[UNR], x2[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const long long gi = gbase + i0 + u * nt;
+            const bool ok = (i0 + u * nt < C * FNP) && gi < gend;
+            cu[u] = ok ? a.cur[gi] : 0.0;
+            ba[u] = (ok && a.base) ? a.base[gi] : 0.0;
+            x2[u] = (ok && a.x2) ? a.x2[gi] : 0.0;
         }
-        a.out[gi] = o;
-        if (!isfinite(o)) bad |= 2;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int i = i0 + u * nt;
+            const long long gi = gbase + i;
+            if (i >= C * FNP || gi >= gend) continue;
+            const int c = i / FNP, r = i - c * FNP;
+            const int f = r / NP, j = r - f * NP;
+            const double L = pref * (double)V[f * CNP + c * NAP + ppos<P>(j)];
+            double o = a.c_cur * cu[u] + a.c_L * dt * L;
+            if (a.base) o += a.c_base * ba[u];
+            if (a.out2) a.out2[gi] = a.d_cur * cu[u] + a.d_L * dt * L + (a.x2 ? a.d_x2 * x2[u] : 0.0);
+            a.out[gi] = o;
+            if (!isfinite(o)) bad |= 2;
+        }
     }
     if (bad) atomicOr(blkflag, bad);
     __syncthreads();
@@ -794,7 +967,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
             double Aa = 0.0, Tt = 0.0, ad = 0.0, td = 0.0;
             for (int m = 0; m < NP; ++m) {
                 const double x = wr[m];
-                const double xd = pref * (double)V[cl * NP + m];
+                const double xd = pref * (double)V[cl * NAP + ppos<P>(m)];
                 Aa += x * x;
                 ad += x * xd;
                 bool tp = false;
@@ -837,8 +1010,8 @@ __global__ void __launch_bounds__(512) vol_kernel_batched(const BoxDesc *boxes, 
     const long long b = xcd_block(blockIdx.x, gridDim.x);
     const int i = owner_box(boxes, nbox, b, 0);
     const BoxDesc &B = boxes[i];
-    const Phys ph = B.ph;
-    const Geo geo = B.geo;
+    const Phys &ph = B.ph;
+    const Geo &geo = B.geo;
     VolArgs a;
     a.cur = B.reg[sd.cur];
     a.base = sd.base >= 0 ? B.reg[sd.base] : nullptr;
@@ -866,7 +1039,7 @@ __global__ void __launch_bounds__(512) vol_kernel_batched(const BoxDesc *boxes, 
 template <int D, int P, typename T, int PH>
 size_t vol_lds_bytes(int C, int Fx)
 {
-    constexpr int NP = ipow(P, D);
+    constexpr int NP = Pad<P>::PP * ipow(P, D - 1);   // padded per-cell array
     constexpr int F = Fld<D, PH>::F;
     const size_t hdr = ((C * (2 * D * sizeof(long long) + sizeof(double)) + sizeof(int) + 15) / 16) * 16;
     return hdr + sizeof(T) * ((size_t)2 * C * Fx * NP + (size_t)C * D * F * NP);
@@ -951,8 +1124,8 @@ __global__ void __launch_bounds__(512) cfl_kernel_batched(const BoxDesc *boxes, 
     extern __shared__ __align__(16) unsigned char smem[];
     const long long b = blockIdx.x;
     const int i = owner_box(boxes, nbox, b, 2);
-    const Phys ph = boxes[i].ph;
-    const Geo geo = boxes[i].geo;
+    const Phys &ph = boxes[i].ph;
+    const Geo &geo = boxes[i].geo;
     CflArgs a;
     a.w = boxes[i].reg[0];
     a.part = boxes[i].cfl_part;

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle as O
-from oracle.compare import state_err
+from oracle.compare import momentum_scale, state_err
 from paper_2208_11131_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -52,7 +52,7 @@ def test_batch_matches_per_box_and_oracle():
             dt = ref.max_dt(wr)[0]
             wr, _ = ref.step(wr, dt)
         assert abs(dts_g[i] - dt) <= 1e-14 * dt
-        assert state_err(wg[i].cpu().numpy(), wr, 2) <= 1e-12, i
+        assert state_err(wg[i].cpu().numpy(), wr, 2, mom_scale=momentum_scale(ref, wr)) <= 1e-12, i
 
 
 def test_batch_graph_replays_after_pointer_change():

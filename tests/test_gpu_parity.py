@@ -18,7 +18,7 @@ import pytest
 import torch
 
 import oracle as O
-from oracle.compare import cfl_rate, rhs_err, state_err
+from oracle.compare import cfl_rate, momentum_scale, rhs_err, state_err
 from paper_2208_11131_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -50,12 +50,12 @@ def pair(dim, n, order, gamma=1.4, nu=0.0, kappa=None, av=None, bc=None, precisi
 
 def relerr(a, b, ref):
     """State error, field groups rho / momentum / energy / alpha."""
-    return state_err(a, b, ref.dim)
+    return state_err(a, b, ref.dim, mom_scale=momentum_scale(ref, b))
 
 
 def rerr(L, Lr, w, ref):
     """RHS error relative to max(||L_g||, rate ||w_g||), rate = 2p(c+|v|)/h."""
-    return rhs_err(L, Lr, w, ref.dim, cfl_rate(ref, w))
+    return rhs_err(L, Lr, w, ref.dim, cfl_rate(ref, w), mom_scale=momentum_scale(ref, w))
 
 
 def state(dim, n, order, prob, seed, vbase=(0, 0, 0)):
@@ -363,4 +363,42 @@ def test_full_size_sampled(cfg):
     wh = w.cpu().numpy()
     cells = _sampled_cells(ref.ncells, 24, rng)
     Lr = ref.rhs_cells(wh, cells, R_prev=np.zeros(ref.ncells) if ref.av is not None else None)
-    assert rhs_err(L[cells], Lr, wh[cells], ref.dim, cfl_rate(ref, wh)) <= 1e-12
+    assert rhs_err(L[cells], Lr, wh, ref.dim, cfl_rate(ref, wh), mom_scale=momentum_scale(ref, wh)) <= 1e-12
+
+
+def test_fp32_bulk_density_wave_run():
+    """Density wave, full run to t = 0.1 with FP32 bulk arithmetic against
+    the FP64 oracle run: mean absolute density-coefficient error <= 1e-6."""
+    order, n, T = 3, 16, 0.1
+    say("fp32 density wave run")
+    gpu, ref = pair(2, (n, n), order, gamma=5.0 / 3.0, cfl=0.3, precision="fp32")
+    w0 = W.density_wave(order, n).numpy()
+    w = torch.tensor(w0, device="cuda")
+    wr = w0
+    t = 0.0
+    while t < T - 1e-14:
+        dt = min(ref.max_dt(wr)[0], T - t)
+        gpu.step(w, dt)
+        wr, _ = ref.step(wr, dt)
+        t += dt
+    err = np.abs(w.cpu().numpy()[:, 0] - wr[:, 0]).mean()
+    say("fp32 density wave mean |drho| =", err)
+    assert err <= 1e-6
+
+
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_fp32_bulk_kelvin_helmholtz_steps(order):
+    """Shear layer (16 x 32), 10 steps in FP32 bulk vs the FP64 oracle."""
+    nx, ny = 16, 32
+    say("fp32 KH steps", order)
+    gpu, ref = pair(2, (nx, ny), order, gamma=5.0 / 3.0, nu=1e-4, precision="fp32")
+    w0 = W.kelvin_helmholtz(order, nx, ny).numpy()
+    w = torch.tensor(w0, device="cuda")
+    wr = w0
+    dt = ref.max_dt(w0)[0]
+    for _ in range(10):
+        gpu.step(w, dt)
+        wr, _ = ref.step(wr, dt)
+    e = relerr(w.cpu().numpy(), wr, ref)
+    say("fp32 KH p=%d 10-step state error %.3e" % (order, e))
+    assert e <= 1e-5
