@@ -92,13 +92,15 @@ def candidates_face(K):
     return out
 
 
-def tune(configs, steps=2, log=sys.stderr):
+def tune(configs, steps=3, log=sys.stderr):
     rows = []
     for dim, order, prec, phys in configs:
         w0, f, args = _state(dim, order, phys)
         NP, K = order ** dim, order ** (dim - 1)
-        best_v, best_f = None, None
         base, used = _time(args, order, prec, w0, f, {}, steps)
+        # the built-in choice is a candidate too
+        best_v = (base["vol"], used[0], used[1])
+        best_f = (base["face"], used[2], used[3])
         for C, T in candidates_vol(NP):
             try:
                 t, _ = _time(args, order, prec, w0, f, dict(cells_per_block=C, vol_threads=T), steps)
