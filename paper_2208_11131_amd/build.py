@@ -2,7 +2,10 @@
 
 Every .hip unit under csrc/ is compiled with hipcc in parallel, then linked
 into paper_2208_11131_amd/libdgmi.so.  Packed-FP32 instruction selection is
-disabled for all device code (-target-feature -packed-fp32-ops).
+disabled for all device code (-target-feature -packed-fp32-ops).  Floating-
+point contraction is limited to single expressions (-ffp-contract=on), so the
+rounding of every kernel variant built from the same source is the same and
+results do not depend on the launch tile.
 """
 import os
 import subprocess
@@ -16,7 +19,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdgmi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 

@@ -14,6 +14,7 @@
 
 #include "dg.h"
 #include "dg_common.hpp"
+#include "dg_tiles.hpp"
 #include "dg_registry.hpp"
 
 using dgk::KernelSet;
@@ -321,19 +322,15 @@ __global__ void totals_final(const double *part, int nblk, int Fc, double *out)
 
 int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
-struct TileEntry {
-    int dim, order, prec, phys, forced, vol_C, vol_T, face_C, face_T;
-};
-
-const TileEntry kTiles[] = {
-#include "dg_tiles.inc"
-    {0, 0, 0, 0, 0, 0, 0, 0, 0}};
+using dgk::TileEntry;
 
 // Tuned tiles for this (dim, order, precision, physics, forcing), if any.
 const TileEntry *find_tiles(int dim, int order, int prec, int phys, int forced)
 {
-    for (const TileEntry &t : kTiles)
+    for (size_t i = 0; i < dgk::kNumTiles; ++i) {
+        const TileEntry &t = dgk::kTiles[i];
         if (t.dim == dim && t.order == order && t.prec == prec && t.phys == phys && t.forced == forced) return &t;
+    }
     return nullptr;
 }
 
@@ -354,6 +351,7 @@ struct dg_ctx {
     bool grad;
     int phys;    // 0 Euler, 1 Navier-Stokes, 2 artificial viscosity
     KernelSet ks, ks64;
+    const void *vol_fixed[2];   // fixed-tile volume kernels (no forcing / forcing) for the tile in use, or null
     int vol_C, vol_T, face_C, face_T, cfl_C, cfl_T, cfl_blocks;
     size_t vol_lds, vol_lds_forced, face_lds, cfl_lds;
     int stages;
@@ -398,6 +396,14 @@ void get_kernels(int dim, int prec, int P, int phys, KernelSet *k)
         (prec == DG_PREC_FP64 ? dgk::dgk_get_2d_f64 : dgk::dgk_get_2d_f32)(P, phys, k);
     else
         (prec == DG_PREC_FP64 ? dgk::dgk_get_3d_f64 : dgk::dgk_get_3d_f32)(P, phys, k);
+}
+
+// Fixed-tile volume kernel of the tuned table for this tile, if one was built.
+const void *get_vol_fixed(int dim, int prec, int P, int phys, int C, int NT, int forced)
+{
+    if (dim == 2)
+        return (prec == DG_PREC_FP64 ? dgk::dgk_vol_fixed_2d_f64 : dgk::dgk_vol_fixed_2d_f32)(P, phys, C, NT, forced);
+    return (prec == DG_PREC_FP64 ? dgk::dgk_vol_fixed_3d_f64 : dgk::dgk_vol_fixed_3d_f32)(P, phys, C, NT, forced);
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
@@ -449,7 +455,9 @@ dg_status stage(dg_ctx *c, dgk::VolArgs va, hipStream_t s)
     va.cells_per_block = c->vol_C;
     void *vargs[] = {&c->ph, &c->geo, &va};
     dim3 vg((unsigned)((c->ncells + c->vol_C - 1) / c->vol_C));
-    return launch(c, 1, c->ks.vol, vg, dim3(c->vol_T), vargs, c->forcing ? c->vol_lds_forced : c->vol_lds, s);
+    const void *vf = c->vol_fixed[c->forcing ? 1 : 0];
+    return launch(c, 1, vf ? vf : c->ks.vol, vg, dim3(c->vol_T), vargs, c->forcing ? c->vol_lds_forced : c->vol_lds,
+                  s);
 }
 
 dgk::VolArgs blank_args()
@@ -587,6 +595,11 @@ const char *dg_status_str(dg_status s)
     return "unknown status";
 }
 
+// Cell and face indices are 32-bit inside the kernels (coordinates are
+// recovered with 32-bit divisions): every axis product of (n[a] + 1) must
+// stay below 2^31.
+static const long long kMaxIndex = 2147483647LL;
+
 dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, double kappa, const dg_av_params *av,
                   const dg_options *opt, dg_ctx **out)
 {
@@ -606,8 +619,11 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         return DG_EINVAL;
     const int d = mesh->dim;
     double h = 0.0;
+    long long cells = 1;
     for (int a = 0; a < d; ++a) {
         if (mesh->n[a] < 1 || !(mesh->hi[a] > mesh->lo[a])) return DG_EINVAL;
+        cells *= (long long)mesh->n[a] + 1;     // bounds the face counts too
+        if (cells > kMaxIndex) return DG_EINVAL;
         if (mesh->bc[a] != DG_BC_PERIODIC && mesh->bc[a] != DG_BC_OUTFLOW) return DG_EINVAL;
         const double ha = (mesh->hi[a] - mesh->lo[a]) / mesh->n[a];
         if (a == 0)
@@ -742,6 +758,11 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     }
     const size_t lim = LDS_MAX;
     (void)hipFuncSetAttribute(c->ks.vol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+    for (int fo = 0; fo < 2; ++fo) {
+        c->vol_fixed[fo] = get_vol_fixed(d, c->precision, order, c->phys, c->vol_C, c->vol_T, fo);
+        if (c->vol_fixed[fo])
+            (void)hipFuncSetAttribute(c->vol_fixed[fo], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+    }
     (void)hipFuncSetAttribute(c->ks.face, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
     (void)hipFuncSetAttribute(c->ks64.cfl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
 

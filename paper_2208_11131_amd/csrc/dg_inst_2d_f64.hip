@@ -47,6 +47,11 @@ void dgk_get_2d_f64(int P, int ph, KernelSet *k)
     }
 }
 
+const void *dgk_vol_fixed_2d_f64(int order, int phys, int C, int NT, int forced)
+{
+    return find_fixed_vol<2, 0, double>(order, phys, C, NT, forced, std::make_index_sequence<kNumTiles>{});
+}
+
 int dgk_upload_2d_f64(const Tab<double> *d, const Tab<float> *f)
 {
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_tabd), d, sizeof(Tab<double>) * (MAXP + 1)) != hipSuccess) return -1;

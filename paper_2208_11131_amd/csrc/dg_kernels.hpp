@@ -19,7 +19,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "dg_common.hpp"
+#include "dg_tiles.hpp"
 
 namespace dgk {
 
@@ -141,48 +144,71 @@ __device__ __forceinline__ int pad_line_offset(int q)
     return a * NAP + (t % P) + PP * (t / P);
 }
 
-template <int P, int DA, int AX, typename T, int MAT, bool ACC>
+template <int P, int DA, int AX, typename T, int MAT, bool ACC, int NTC = 0>
 __device__ __forceinline__ void line_pass_pad(const T *__restrict__ in, T *__restrict__ out, int narr)
 {
     constexpr int PP = Pad<P>::PP;
     constexpr int NL = ipow(P, DA - 1);                  // lines per array
     constexpr int S = (AX == 0) ? 1 : (AX == 1 ? PP : PP * P);
     const int nitems = narr * NL;
-    const int nt = blockDim.x;
-    for (int q = threadIdx.x; q < nitems; q += 2 * nt) {
-        const bool two = q + nt < nitems;
-        const int o0 = pad_line_offset<P, DA, AX>(q);
-        const int o1 = two ? pad_line_offset<P, DA, AX>(q + nt) : o0;
-        T x0[P], x1[P], y0[P], y1[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            x0[k] = in[o0 + k * S];
-            x1[k] = in[o1 + k * S];
-        }
-        if (ACC) {
-#pragma unroll
-            for (int i = 0; i < P; ++i) {
-                y0[i] = out[o0 + i * S];
-                y1[i] = out[o1 + i * S];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            T a0 = ACC ? y0[i] : T(0), a1 = ACC ? y1[i] : T(0);
+    const int nt = NTC > 0 ? NTC : (int)blockDim.x;      // NTC: block size fixed at compile time
+    // rounds of 2 nt lines (two per thread) while the block has that many,
+    // then at most one round of single lines; the choice is uniform
+    for (int b0 = 0; b0 < nitems; b0 += 2 * nt) {
+        const int q = b0 + threadIdx.x;
+        if (b0 + nt < nitems) {
+            const bool two = q + nt < nitems;
+            const int o0 = pad_line_offset<P, DA, AX>(q);
+            const int o1 = two ? pad_line_offset<P, DA, AX>(q + nt) : o0;
+            T x0[P], x1[P], y0[P], y1[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const T m = mat<P, T, MAT>(k, i);
-                a0 = fma(m, x0[k], a0);
-                a1 = fma(m, x1[k], a1);
+                x0[k] = in[o0 + k * S];
+                x1[k] = in[o1 + k * S];
             }
-            y0[i] = a0;
-            y1[i] = a1;
-        }
+            if (ACC) {
 #pragma unroll
-        for (int i = 0; i < P; ++i) out[o0 + i * S] = y0[i];
-        if (two) {
+                for (int i = 0; i < P; ++i) {
+                    y0[i] = out[o0 + i * S];
+                    y1[i] = out[o1 + i * S];
+                }
+            }
 #pragma unroll
-            for (int i = 0; i < P; ++i) out[o1 + i * S] = y1[i];
+            for (int i = 0; i < P; ++i) {
+                T a0 = ACC ? y0[i] : T(0), a1 = ACC ? y1[i] : T(0);
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const T m = mat<P, T, MAT>(k, i);
+                    a0 = fma(m, x0[k], a0);
+                    a1 = fma(m, x1[k], a1);
+                }
+                y0[i] = a0;
+                y1[i] = a1;
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) out[o0 + i * S] = y0[i];
+            if (two) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) out[o1 + i * S] = y1[i];
+            }
+        } else if (q < nitems) {
+            const int o0 = pad_line_offset<P, DA, AX>(q);
+            T x0[P], y0[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) x0[k] = in[o0 + k * S];
+            if (ACC) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) y0[i] = out[o0 + i * S];
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                T a0 = ACC ? y0[i] : T(0);
+#pragma unroll
+                for (int k = 0; k < P; ++k) a0 = fma(mat<P, T, MAT>(k, i), x0[k], a0);
+                y0[i] = a0;
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) out[o0 + i * S] = y0[i];
         }
     }
 }
@@ -362,18 +388,21 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     const int tid = threadIdx.x, nt = blockDim.x;
     const int Q = C * F * NAF;
     const int na = geo.n[AX], nfa = geo.nf[AX];
-    const int npl = (nfa + C - 1) / C;
-    const long long line = pen_id / npl;
-    const int a0 = (int)(pen_id - line * npl) * C;
+    // pencil coordinates in 32 bits (the host bounds the counts by 2^31)
+    const unsigned npl = (unsigned)((nfa + C - 1) / C);
+    const unsigned line = (unsigned)pen_id / npl;
+    const int a0 = (int)((unsigned)pen_id - line * npl) * C;
     const int nface = min(C, nfa - a0);
     int co[3] = {0, 0, 0};
     {
-        long long r = line;
+        unsigned r = line;
 #pragma unroll
         for (int b = 0; b < 3; ++b)
             if (b != AX) {
-                co[b] = (int)(r % geo.n[b]);
-                r /= geo.n[b];
+                const unsigned nb = (unsigned)geo.n[b];
+                const unsigned q = r / nb;
+                co[b] = (int)(r - q * nb);
+                r = q;
             }
     }
 
@@ -389,7 +418,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         int ca = a0 + s - 1;
         int m = 0;
         if (geo.bc[AX] == 0) {
-            ca = ((ca % na) + na) % na;   // pencils may be longer than the axis
+            if (ca < 0 || ca >= na) ca = ((ca % na) + na) % na;   // pencils may be longer than the axis
         } else {
             if (ca < 0) {
                 ca = 0;
@@ -643,7 +672,10 @@ size_t face_lds_bytes(int C)
 // volume kernel
 // ---------------------------------------------------------------------------
 
-template <int D, int P, typename T, int PH>
+// CC, NTC, FO: cells per block, threads per block and forcing (0 off, 1 on)
+// fixed at compile time (0 / 0 / -1 = taken from the launch).  Fixing them
+// removes the runtime tile arithmetic; the results are the same bits.
+template <int D, int P, typename T, int PH, int CC = 0, int NTC = 0, int FO = -1>
 __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const VolArgs &a, unsigned char *smem,
                                          long long tile)
 {
@@ -653,12 +685,12 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     constexpr int F = Fld<D, PH>::F;
     constexpr bool GRAD = Fld<D, PH>::GRAD;
     constexpr int FNP = F * NP;
-    const bool forced = a.forcing != nullptr;
+    const bool forced = FO >= 0 ? FO == 1 : a.forcing != nullptr;
     const int Fx = F + (forced ? D : 0);
-    const int C = a.cells_per_block;
+    const int C = CC > 0 ? CC : a.cells_per_block;
     constexpr int NAP = Pad<P>::PP * NP / P;  // padded per-cell array
     const int CNP = C * NAP;                  // one field of the tile
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, nt = NTC > 0 ? NTC : (int)blockDim.x;
     const long long NC = geo.ncells;
     const long long c0 = tile * C;
 
@@ -721,21 +753,18 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     for (int cl = tid; cl < C; cl += nt) {
         long long cc = c0 + cl;
         if (cc >= NC) cc = NC - 1;
-        int co[3];
-        long long t = cc;
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            co[b] = (int)(t % geo.n[b]);
-            t /= geo.n[b];
-        }
+        // coordinates and face indices in 32 bits (the host bounds them by 2^31)
+        const unsigned u = (unsigned)cc, n0 = (unsigned)geo.n[0], n1 = (unsigned)geo.n[1];
+        const unsigned r0 = u / n0;
+        const unsigned co[3] = {u - r0 * n0, r0 % n1, r0 / n1};
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) {
-            const int nfa = geo.nf[ax];
-            long long flo = 0, fhi = 0, mul = 1;
+            const unsigned nfa = (unsigned)geo.nf[ax];
+            unsigned flo = 0, fhi = 0, mul = 1;
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                const int nb = (b == ax) ? nfa : geo.n[b];
-                int ilo = co[b], ihi = co[b];
+                const unsigned nb = (b == ax) ? nfa : (unsigned)geo.n[b];
+                unsigned ilo = co[b], ihi = co[b];
                 if (b == ax) {
                     ihi = co[b] + 1;
                     if (ihi >= nfa) ihi -= nfa;   // periodic wrap (outflow has nf = n + 1)
@@ -771,12 +800,12 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     __syncthreads();
 
     // 2. point values of all fields: one operator pass per axis
-    line_pass_pad<P, D, 0, T, M_B, false>(X0, X1, Fx * C);
+    line_pass_pad<P, D, 0, T, M_B, false, NTC>(X0, X1, Fx * C);
     __syncthreads();
-    line_pass_pad<P, D, 1, T, M_B, false>(X1, X0, Fx * C);
+    line_pass_pad<P, D, 1, T, M_B, false, NTC>(X1, X0, Fx * C);
     __syncthreads();
     if (D == 3) {
-        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_B, false>(X0, X1, Fx * C);
+        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_B, false, NTC>(X0, X1, Fx * C);
         __syncthreads();
     }
     T *U = (D == 3) ? X1 : X0;
@@ -784,9 +813,9 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
 
     // 3. collocation gradients d/dxi of the stored fields
     if (GRAD) {
-        line_pass_pad<P, D, 0, T, M_D, false>(U, G, F * C);
-        line_pass_pad<P, D, 1, T, M_D, false>(U, G + F * CNP, F * C);
-        if (D == 3) line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_D, false>(U, G + 2 * F * CNP, F * C);
+        line_pass_pad<P, D, 0, T, M_D, false, NTC>(U, G, F * C);
+        line_pass_pad<P, D, 1, T, M_D, false, NTC>(U, G + F * CNP, F * C);
+        if (D == 3) line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_D, false, NTC>(U, G + 2 * F * CNP, F * C);
         __syncthreads();
     }
 
@@ -865,12 +894,12 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     __syncthreads();
 
     // 5. Q += sum_a D_a^T (w f_a)
-    line_pass_pad<P, D, 0, T, M_DT, true>(G, U, Fc * C);
+    line_pass_pad<P, D, 0, T, M_DT, true, NTC>(G, U, Fc * C);
     __syncthreads();
-    line_pass_pad<P, D, 1, T, M_DT, true>(G + F * CNP, U, Fc * C);
+    line_pass_pad<P, D, 1, T, M_DT, true, NTC>(G + F * CNP, U, Fc * C);
     __syncthreads();
     if (D == 3) {
-        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_DT, true>(G + 2 * F * CNP, U, Fc * C);
+        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_DT, true, NTC>(G + 2 * F * CNP, U, Fc * C);
         __syncthreads();
     }
 
@@ -910,12 +939,12 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     }
 
     // 7. point -> modal projection of every stored field
-    line_pass_pad<P, D, 0, T, M_BT, false>(U, Wk, F * C);
+    line_pass_pad<P, D, 0, T, M_BT, false, NTC>(U, Wk, F * C);
     __syncthreads();
-    line_pass_pad<P, D, 1, T, M_BT, false>(Wk, U, F * C);
+    line_pass_pad<P, D, 1, T, M_BT, false, NTC>(Wk, U, F * C);
     __syncthreads();
     if (D == 3) {
-        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_BT, false>(U, Wk, F * C);
+        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_BT, false, NTC>(U, Wk, F * C);
         __syncthreads();
     }
     const T *V = (D == 3) ? Wk : U;
@@ -1000,6 +1029,18 @@ __global__ void __launch_bounds__(512) vol_kernel(Phys ph, Geo geo, VolArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     vol_body<D, P, T, PH>(ph, geo, a, smem, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Volume kernel with the launch tile (C cells, NT threads) and the forcing
+// switch fixed at compile time; instantiated for the tuned tiles.  The host
+// launches it only with blockDim.x == NT, cells_per_block == C and forcing
+// present iff FO == 1.
+template <int D, int P, typename T, int PH, int C, int NT, int FO>
+__global__ void __launch_bounds__(NT) vol_kernel_fixed(Phys ph, Geo geo, VolArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if ((FO == 1) != (a.forcing != nullptr) || a.cells_per_block != C) return;   // host selection error
+    vol_body<D, P, T, PH, C, NT, FO>(ph, geo, a, smem, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // Grouped volume/stage kernel over every box of one (dim, order) group.
@@ -1138,6 +1179,34 @@ size_t cfl_lds_bytes(int C, int nt)
 {
     constexpr int NP = ipow(P, D);
     return sizeof(double) * ((size_t)2 * C * (D + 2) * NP + 2 * (size_t)nt);
+}
+
+// ---------------------------------------------------------------------------
+// fixed-tile volume kernels of the tuned table
+// ---------------------------------------------------------------------------
+
+// Entry I of the tuned table as a fixed-tile kernel of this (dim, precision)
+// unit, or an empty record.  FO = 1 (forcing) variants exist for 3D entries.
+template <int DIM, int PREC, typename T, size_t I, int FO>
+FixedVol fixed_vol_entry()
+{
+    constexpr TileEntry e = kTiles[I];
+    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 2 &&
+                  e.vol_C > 0 && e.vol_T >= 64 && e.vol_T <= 512 && e.vol_T % 64 == 0 && (FO == 0 || DIM == 3))
+        return FixedVol{e.order, e.phys, e.vol_C, e.vol_T, FO,
+                        (const void *)&vol_kernel_fixed<DIM, e.order, T, e.phys, e.vol_C, e.vol_T, FO>};
+    else
+        return FixedVol{0, 0, 0, 0, 0, nullptr};
+}
+
+template <int DIM, int PREC, typename T, size_t... I>
+const void *find_fixed_vol(int order, int phys, int C, int NT, int forced, std::index_sequence<I...>)
+{
+    static const FixedVol tab[] = {fixed_vol_entry<DIM, PREC, T, I, 0>()...,
+                                   fixed_vol_entry<DIM, PREC, T, I, 1>()..., FixedVol{0, 0, 0, 0, 0, nullptr}};
+    for (const FixedVol &f : tab)
+        if (f.fn && f.order == order && f.phys == phys && f.C == C && f.NT == NT && f.forced == forced) return f.fn;
+    return nullptr;
 }
 
 }  // namespace dgk

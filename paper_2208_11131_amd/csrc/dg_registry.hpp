@@ -25,6 +25,12 @@ void dgk_get_2d_f64(int P, int ph, KernelSet *k);
 void dgk_get_3d_f64(int P, int ph, KernelSet *k);
 void dgk_get_2d_f32(int P, int ph, KernelSet *k);
 void dgk_get_3d_f32(int P, int ph, KernelSet *k);
+// Fixed-tile volume kernel for (order, physics, cells per block, threads,
+// forcing) if the tuned table has one for this unit, else null.
+const void *dgk_vol_fixed_2d_f64(int order, int phys, int C, int NT, int forced);
+const void *dgk_vol_fixed_3d_f64(int order, int phys, int C, int NT, int forced);
+const void *dgk_vol_fixed_2d_f32(int order, int phys, int C, int NT, int forced);
+const void *dgk_vol_fixed_3d_f32(int order, int phys, int C, int NT, int forced);
 int dgk_upload_2d_f64(const Tab<double> *d, const Tab<float> *f);
 int dgk_upload_3d_f64(const Tab<double> *d, const Tab<float> *f);
 int dgk_upload_2d_f32(const Tab<double> *d, const Tab<float> *f);
