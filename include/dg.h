@@ -97,7 +97,9 @@ void dg_options_defaults(dg_options *opt);
  * library-owned device buffers (RK registers, face-flux buffer, sensor
  * scalars, time-step scalars).  gamma > 1; nu (kinematic viscosity) and
  * kappa (thermal diffusivity chi of Sec. 3.3) >= 0; av NULL or disabled =
- * no AV field.  Uses the current HIP device.  *out = NULL on error. */
+ * no AV field.  Cell and face indices are 32-bit on the device: the product
+ * over the axes of (n[a] + 1) must not exceed 2^31 - 1 (DG_EINVAL).  Uses
+ * the current HIP device.  *out = NULL on error. */
 dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, double kappa,
                   const dg_av_params *av, const dg_options *opt, dg_ctx **out);
 

@@ -352,6 +352,7 @@ struct dg_ctx {
     int phys;    // 0 Euler, 1 Navier-Stokes, 2 artificial viscosity
     KernelSet ks, ks64;
     const void *vol_fixed[2];   // fixed-tile volume kernels (no forcing / forcing) for the tile in use, or null
+    const void *face_fixed;     // fixed-tile face kernel for the tile in use, or null
     int vol_C, vol_T, face_C, face_T, cfl_C, cfl_T, cfl_blocks;
     size_t vol_lds, vol_lds_forced, face_lds, cfl_lds;
     int stages;
@@ -406,6 +407,14 @@ const void *get_vol_fixed(int dim, int prec, int P, int phys, int C, int NT, int
     return (prec == DG_PREC_FP64 ? dgk::dgk_vol_fixed_3d_f64 : dgk::dgk_vol_fixed_3d_f32)(P, phys, C, NT, forced);
 }
 
+// Fixed-tile face kernel of the tuned table for this tile, if one was built.
+const void *get_face_fixed(int dim, int prec, int P, int phys, int C, int NT)
+{
+    if (dim == 2)
+        return (prec == DG_PREC_FP64 ? dgk::dgk_face_fixed_2d_f64 : dgk::dgk_face_fixed_2d_f32)(P, phys, C, NT);
+    return (prec == DG_PREC_FP64 ? dgk::dgk_face_fixed_3d_f64 : dgk::dgk_face_fixed_3d_f32)(P, phys, C, NT);
+}
+
 constexpr size_t LDS_MAX = 160 * 1024;
 
 constexpr long long EV_MAX = 16384;
@@ -447,7 +456,8 @@ dg_status stage(dg_ctx *c, dgk::VolArgs va, hipStream_t s)
     fa.faces_per_block = c->face_C;
     void *fargs[] = {&c->ph, &c->geo, &fa};
     dim3 fg((unsigned)dgk::face_pencils(c->geo, c->dim, c->face_C), (unsigned)c->dim);
-    dg_status st = launch(c, 0, c->ks.face, fg, dim3(c->face_T), fargs, c->face_lds, s);
+    dg_status st = launch(c, 0, c->face_fixed ? c->face_fixed : c->ks.face, fg, dim3(c->face_T), fargs,
+                          c->face_lds, s);
     if (st != DG_OK) return st;
     va.fb = c->fb;
     va.forcing = c->forcing;
@@ -764,6 +774,9 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
             (void)hipFuncSetAttribute(c->vol_fixed[fo], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
     }
     (void)hipFuncSetAttribute(c->ks.face, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+    c->face_fixed = get_face_fixed(d, c->precision, order, c->phys, c->face_C, c->face_T);
+    if (c->face_fixed)
+        (void)hipFuncSetAttribute(c->face_fixed, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
     (void)hipFuncSetAttribute(c->ks64.cfl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
 
     // buffers

@@ -52,6 +52,11 @@ const void *dgk_vol_fixed_3d_f64(int order, int phys, int C, int NT, int forced)
     return find_fixed_vol<3, 0, double>(order, phys, C, NT, forced, std::make_index_sequence<kNumTiles>{});
 }
 
+const void *dgk_face_fixed_3d_f64(int order, int phys, int C, int NT)
+{
+    return find_fixed_face<3, 0, double>(order, phys, C, NT, std::make_index_sequence<kNumTiles>{});
+}
+
 int dgk_upload_3d_f64(const Tab<double> *d, const Tab<float> *f)
 {
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_tabd), d, sizeof(Tab<double>) * (MAXP + 1)) != hipSuccess) return -1;

@@ -368,7 +368,9 @@ __device__ __forceinline__ T clamp_alpha(T al, T amax)
 // transverse coordinates).  It loads the C + 1 cells that these faces
 // separate once, so every cell is read about once per direction.
 
-template <int D, int P, int AX, typename T, int PH>
+// CC, NTC: faces per pencil and threads per block fixed at compile time (0 =
+// taken from the launch); same results either way.
+template <int D, int P, int AX, typename T, int PH, int CC = 0, int NTC = 0>
 __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const FaceArgs &a, unsigned char *smem,
                                           long long pen_id)
 {
@@ -384,8 +386,8 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     constexpr int NAP = PP * NP / P;                      // padded cell array
     constexpr int NAF = (D == 3) ? PP * P : PP;           // padded face array
     constexpr int SP = (AX == 0) ? 1 : (AX == 1 ? PP : PP * P);   // padded stride along AX
-    const int C = a.faces_per_block;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int C = CC > 0 ? CC : a.faces_per_block;
+    const int tid = threadIdx.x, nt = NTC > 0 ? NTC : (int)blockDim.x;
     const int Q = C * F * NAF;
     const int na = geo.n[AX], nfa = geo.nf[AX];
     // pencil coordinates in 32 bits (the host bounds the counts by 2^31)
@@ -501,8 +503,8 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     // transverse transforms to the face Gauss points
     const T *tLp, *tRp, *utp = nullptr, *rnp = nullptr, *d1p = nullptr, *d2p = nullptr;
     if (D == 2) {
-        line_pass_pad<P, 1, 0, T, M_B, false>(A, Sx, NA * C * F);
-        if (GRAD) line_pass_pad<P, 1, 0, T, M_BD, false>(A + 2 * Q, Sx + 4 * Q, C * F);
+        line_pass_pad<P, 1, 0, T, M_B, false, NTC>(A, Sx, NA * C * F);
+        if (GRAD) line_pass_pad<P, 1, 0, T, M_BD, false, NTC>(A + 2 * Q, Sx + 4 * Q, C * F);
         __syncthreads();
         tLp = Sx;
         tRp = Sx + Q;
@@ -511,14 +513,14 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         d1p = Sx + 4 * Q;
     } else {
         // (t1, t2) = transverse axes of the face in ascending order
-        line_pass_pad<P, 2, 0, T, M_B, false>(A, Sx, NA * C * F);
-        if (GRAD) line_pass_pad<P, 2, 0, T, M_BD, false>(A + 2 * Q, Sx + 4 * Q, C * F);
+        line_pass_pad<P, 2, 0, T, M_B, false, NTC>(A, Sx, NA * C * F);
+        if (GRAD) line_pass_pad<P, 2, 0, T, M_BD, false, NTC>(A + 2 * Q, Sx + 4 * Q, C * F);
         __syncthreads();
-        line_pass_pad<P, 2, 1, T, M_B, false>(Sx, A, NA * C * F);
+        line_pass_pad<P, 2, 1, T, M_B, false, NTC>(Sx, A, NA * C * F);
         __syncthreads();
         if (GRAD) {
-            line_pass_pad<P, 2, 1, T, M_BD, false>(Sx + 2 * Q, Sx, C * F);
-            line_pass_pad<P, 2, 1, T, M_B, false>(Sx + 4 * Q, Sx + Q, C * F);
+            line_pass_pad<P, 2, 1, T, M_BD, false, NTC>(Sx + 2 * Q, Sx, C * F);
+            line_pass_pad<P, 2, 1, T, M_B, false, NTC>(Sx + 4 * Q, Sx + Q, C * F);
             __syncthreads();
         }
         tLp = A;
@@ -594,16 +596,16 @@ __device__ __forceinline__ long long pencils(const Geo &geo, int ax, int C)
     return npen;
 }
 
-template <int D, int P, typename T, int PH>
+template <int D, int P, typename T, int PH, int CC = 0, int NTC = 0>
 __device__ __forceinline__ void face_dispatch(const Phys &ph, const Geo &geo, const FaceArgs &a, unsigned char *smem,
                                               int ax, long long pen)
 {
     if (ax == 0)
-        face_body<D, P, 0, T, PH>(ph, geo, a, smem, pen);
+        face_body<D, P, 0, T, PH, CC, NTC>(ph, geo, a, smem, pen);
     else if (ax == 1)
-        face_body<D, P, 1, T, PH>(ph, geo, a, smem, pen);
+        face_body<D, P, 1, T, PH, CC, NTC>(ph, geo, a, smem, pen);
     else if (D == 3)
-        face_body<D, P, (D == 3 ? 2 : 0), T, PH>(ph, geo, a, smem, pen);
+        face_body<D, P, (D == 3 ? 2 : 0), T, PH, CC, NTC>(ph, geo, a, smem, pen);
 }
 
 template <int D, int P, typename T, int PH>
@@ -614,6 +616,20 @@ __global__ void __launch_bounds__(512) face_kernel(Phys ph, Geo geo, FaceArgs a)
     const unsigned bid = xcd_block(blockIdx.x, gridDim.x);
     if ((long long)bid >= pencils(geo, ax, a.faces_per_block)) return;
     face_dispatch<D, P, T, PH>(ph, geo, a, smem, ax, bid);
+}
+
+// Face kernel with the pencil length C and block size NT fixed at compile
+// time; instantiated for the tuned tiles and launched only with
+// blockDim.x == NT and faces_per_block == C.
+template <int D, int P, typename T, int PH, int C, int NT>
+__global__ void __launch_bounds__(NT) face_kernel_fixed(Phys ph, Geo geo, FaceArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (a.faces_per_block != C) return;   // host selection error
+    const int ax = blockIdx.y;
+    const unsigned bid = xcd_block(blockIdx.x, gridDim.x);
+    if ((long long)bid >= pencils(geo, ax, C)) return;
+    face_dispatch<D, P, T, PH, C, NT>(ph, geo, a, smem, ax, bid);
 }
 
 // Index of the box owning flat block b of a grouped launch (uniform scan).
@@ -1197,6 +1213,28 @@ FixedVol fixed_vol_entry()
                         (const void *)&vol_kernel_fixed<DIM, e.order, T, e.phys, e.vol_C, e.vol_T, FO>};
     else
         return FixedVol{0, 0, 0, 0, 0, nullptr};
+}
+
+// Entry I of the tuned table as a fixed-tile face kernel, or an empty record.
+template <int DIM, int PREC, typename T, size_t I>
+FixedVol fixed_face_entry()
+{
+    constexpr TileEntry e = kTiles[I];
+    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 2 &&
+                  e.face_C > 0 && e.face_T >= 64 && e.face_T <= 512 && e.face_T % 64 == 0)
+        return FixedVol{e.order, e.phys, e.face_C, e.face_T, 0,
+                        (const void *)&face_kernel_fixed<DIM, e.order, T, e.phys, e.face_C, e.face_T>};
+    else
+        return FixedVol{0, 0, 0, 0, 0, nullptr};
+}
+
+template <int DIM, int PREC, typename T, size_t... I>
+const void *find_fixed_face(int order, int phys, int C, int NT, std::index_sequence<I...>)
+{
+    static const FixedVol tab[] = {fixed_face_entry<DIM, PREC, T, I>()..., FixedVol{0, 0, 0, 0, 0, nullptr}};
+    for (const FixedVol &f : tab)
+        if (f.fn && f.order == order && f.phys == phys && f.C == C && f.NT == NT) return f.fn;
+    return nullptr;
 }
 
 template <int DIM, int PREC, typename T, size_t... I>

@@ -31,6 +31,11 @@ const void *dgk_vol_fixed_2d_f64(int order, int phys, int C, int NT, int forced)
 const void *dgk_vol_fixed_3d_f64(int order, int phys, int C, int NT, int forced);
 const void *dgk_vol_fixed_2d_f32(int order, int phys, int C, int NT, int forced);
 const void *dgk_vol_fixed_3d_f32(int order, int phys, int C, int NT, int forced);
+// Fixed-tile face kernel for (order, physics, faces per pencil, threads).
+const void *dgk_face_fixed_2d_f64(int order, int phys, int C, int NT);
+const void *dgk_face_fixed_3d_f64(int order, int phys, int C, int NT);
+const void *dgk_face_fixed_2d_f32(int order, int phys, int C, int NT);
+const void *dgk_face_fixed_3d_f32(int order, int phys, int C, int NT);
 int dgk_upload_2d_f64(const Tab<double> *d, const Tab<float> *f);
 int dgk_upload_3d_f64(const Tab<double> *d, const Tab<float> *f);
 int dgk_upload_2d_f32(const Tab<double> *d, const Tab<float> *f);

@@ -1,6 +1,7 @@
 // dg_tiles.hpp -- launch tiles chosen by the autotuner (dg_tiles.inc), as a
 // compile-time table: the host runtime takes its default tiles from it, and
-// the instantiation units build one fixed-tile volume kernel per entry.
+// the instantiation units build one fixed-tile volume and face kernel per
+// entry.
 #pragma once
 #include <stddef.h>
 
@@ -16,7 +17,7 @@ constexpr TileEntry kTiles[] = {
 
 constexpr size_t kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]) - 1;
 
-// Fixed-tile volume kernel of one table entry (host stub), or null.
+// Fixed-tile volume or face kernel of one table entry (host stub), or null.
 struct FixedVol {
     int order, phys, C, NT, forced;
     const void *fn;
