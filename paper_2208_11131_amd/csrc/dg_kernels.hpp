@@ -710,14 +710,18 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     const long long NC = geo.ncells;
     const long long c0 = tile * C;
 
-    // LDS, field-major: X0/X1 [field][cell][point], G [axis][field][cell][point]
-    // (points in the padded layout of Pad<P>)
+    // LDS, field-major: Ub [field][cell][point] (point values, then sources),
+    // G [axis][field][cell][point] (gradients, then fluxes); points in the
+    // padded layout of Pad<P>.  The modal load and the ping-pong buffer of the
+    // contraction passes live in G's space (D F >= F + D arrays), which is
+    // free outside the gradient / flux phases.
     long long *fidx = (long long *)smem;      // [C][D][2] lower/upper face index per axis
     double *cellv = (double *)(fidx + 2 * D * C);   // [C]: wiggle source
     int *blkflag = (int *)(cellv + C);
-    T *X0 = (T *)(smem + ((C * (2 * D * sizeof(long long) + sizeof(double)) + sizeof(int) + 15) / 16) * 16);
-    T *X1 = X0 + Fx * CNP;
-    T *G = X1 + Fx * CNP;
+    T *Ub = (T *)(smem + ((C * (2 * D * sizeof(long long) + sizeof(double)) + sizeof(int) + 15) / 16) * 16);
+    T *G = Ub + Fx * CNP;
+    T *X0 = (D == 3) ? G : Ub;     // the last of the D passes lands in Ub
+    T *X1 = (D == 3) ? Ub : G;
     const Tab<T> &tb = TabSel<T>::get(P);
 
     // 1. load the tile's weights (and forcing coefficients); per-cell data.
@@ -1099,7 +1103,7 @@ size_t vol_lds_bytes(int C, int Fx)
     constexpr int NP = Pad<P>::PP * ipow(P, D - 1);   // padded per-cell array
     constexpr int F = Fld<D, PH>::F;
     const size_t hdr = ((C * (2 * D * sizeof(long long) + sizeof(double)) + sizeof(int) + 15) / 16) * 16;
-    return hdr + sizeof(T) * ((size_t)2 * C * Fx * NP + (size_t)C * D * F * NP);
+    return hdr + sizeof(T) * ((size_t)C * Fx * NP + (size_t)C * D * F * NP);
 }
 
 // ---------------------------------------------------------------------------
