@@ -913,6 +913,32 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     }
     __syncthreads();
 
+    // Global reads of the later phases are issued early, after the flux
+    // phase (the register peak), so their latency overlaps the D^T, lift and
+    // projection passes: the face fluxes of the first NLF lift rounds and the
+    // RK inputs of the first NLD elements of each thread (the rest, if any,
+    // are read where they are used).  With a fixed tile both counts are exact.
+    constexpr int NLF = (CC > 0 && NTC > 0) ? (CC * Fc * K + NTC - 1) / NTC : 1;
+    constexpr int NLD0 = (CC > 0 && NTC > 0) ? (CC * FNP + NTC - 1) / NTC : 2;
+    constexpr int NLD = NLD0 < 8 ? NLD0 : 8;
+    const int nlift = C * Fc * K;
+    const int nel = C * FNP;
+    auto lift_load = [&](int q, T *Fl, T *Fu) {
+        const bool act = q < nlift;
+        const int c = act ? q / (Fc * K) : 0;
+        const int r = q - c * (Fc * K);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            const T *fb = (const T *)a.fb + geo.fb_off[ax];
+            const long long flo = fidx[(c * D + ax) * 2], fhi = fidx[(c * D + ax) * 2 + 1];
+            Fl[ax] = act ? fb[flo * (Fc * K) + r] : T(0);
+            Fu[ax] = act ? fb[fhi * (Fc * K) + r] : T(0);
+        }
+    };
+    T lfl[NLF][D], lfu[NLF][D];
+#pragma unroll
+    for (int rr = 0; rr < NLF; ++rr) lift_load(tid + rr * nt, lfl[rr], lfu[rr]);
+
     // 5. Q += sum_a D_a^T (w f_a)
     line_pass_pad<P, D, 0, T, M_DT, true, NTC>(G, U, Fc * C);
     __syncthreads();
@@ -923,26 +949,26 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         __syncthreads();
     }
 
-    // 6. surface lift in point space: Q(i, k) += L_i(-1) F_lower(k) - L_i(+1) F_upper(k).
-    //    Each round first loads the face fluxes of every axis, then applies
-    //    them axis by axis (a barrier between axes: their lines intersect).
+    const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
+    double pc[NLD], pb[NLD], px[NLD];
+#pragma unroll
+    for (int m = 0; m < NLD; ++m) {
+        const int i = tid + m * nt;
+        const long long gi = gbase + i;
+        const bool ok = i < nel && gi < gend;
+        pc[m] = ok ? a.cur[gi] : 0.0;
+        pb[m] = (ok && a.base) ? a.base[gi] : 0.0;
+        px[m] = (ok && a.x2) ? a.x2[gi] : 0.0;
+    }
+
+    // 6. surface lift in point space: Q(i, k) += L_i(-1) F_lower(k) - L_i(+1) F_upper(k),
+    //    applied axis by axis (a barrier between axes: their lines intersect).
     {
-        const int nlift = C * Fc * K;
-        const int rounds = (nlift + nt - 1) / nt;          // uniform over the block
-        for (int rr = 0; rr < rounds; ++rr) {
-            const int q = tid + rr * nt;
+        auto lift = [&](int q, const T *Fl, const T *Fu) {
             const bool act = q < nlift;
             const int c = act ? q / (Fc * K) : 0;
             const int r = q - c * (Fc * K);
             const int f = act ? r / K : 0, k = act ? r - f * K : 0;
-            T Fl[D], Fu[D];
-#pragma unroll
-            for (int ax = 0; ax < D; ++ax) {
-                const T *fb = (const T *)a.fb + geo.fb_off[ax];
-                const long long flo = fidx[(c * D + ax) * 2], fhi = fidx[(c * D + ax) * 2 + 1];
-                Fl[ax] = act ? fb[flo * (Fc * K) + f * K + k] : T(0);
-                Fu[ax] = act ? fb[fhi * (Fc * K) + f * K + k] : T(0);
-            }
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
                 const int S = (ax == 0) ? 1 : (ax == 1 ? P : P * P);
@@ -955,6 +981,15 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
                 }
                 __syncthreads();
             }
+        };
+        const int rounds = (nlift + nt - 1) / nt;          // uniform over the block
+#pragma unroll
+        for (int rr = 0; rr < NLF; ++rr)
+            if (rr < rounds) lift(tid + rr * nt, lfl[rr], lfu[rr]);
+        for (int rr = NLF; rr < rounds; ++rr) {
+            T Fl[D], Fu[D];
+            lift_load(tid + rr * nt, Fl, Fu);
+            lift(tid + rr * nt, Fl, Fu);
         }
     }
 
@@ -970,15 +1005,30 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     const T *V = (D == 3) ? Wk : U;
 
     // 8. RK combination in FP64 and write-back
-    const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
     const double pref = ph.pref;
     int bad = 0;
-    for (int i0 = tid; i0 < C * FNP; i0 += UNR * nt) {
+    auto combine = [&](int i, long long gi, double cu, double ba, double x2) {
+        const int c = i / FNP, r = i - c * FNP;
+        const int f = r / NP, j = r - f * NP;
+        const double L = pref * (double)V[f * CNP + c * NAP + ppos<P>(j)];
+        double o = a.c_cur * cu + a.c_L * dt * L;
+        if (a.base) o += a.c_base * ba;
+        if (a.out2) a.out2[gi] = a.d_cur * cu + a.d_L * dt * L + (a.x2 ? a.d_x2 * x2 : 0.0);
+        a.out[gi] = o;
+        if (!isfinite(o)) bad |= 2;
+    };
+#pragma unroll
+    for (int m = 0; m < NLD; ++m) {
+        const int i = tid + m * nt;
+        const long long gi = gbase + i;
+        if (i < nel && gi < gend) combine(i, gi, pc[m], pb[m], px[m]);
+    }
+    for (int i0 = tid + NLD * nt; i0 < nel; i0 += UNR * nt) {
         double cu[UNR], ba[UNR], x2[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const long long gi = gbase + i0 + u * nt;
-            const bool ok = (i0 + u * nt < C * FNP) && gi < gend;
+            const bool ok = (i0 + u * nt < nel) && gi < gend;
             cu[u] = ok ? a.cur[gi] : 0.0;
             ba[u] = (ok && a.base) ? a.base[gi] : 0.0;
             x2[u] = (ok && a.x2) ? a.x2[gi] : 0.0;
@@ -987,15 +1037,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         for (int u = 0; u < UNR; ++u) {
             const int i = i0 + u * nt;
             const long long gi = gbase + i;
-            if (i >= C * FNP || gi >= gend) continue;
-            const int c = i / FNP, r = i - c * FNP;
-            const int f = r / NP, j = r - f * NP;
-            const double L = pref * (double)V[f * CNP + c * NAP + ppos<P>(j)];
-            double o = a.c_cur * cu[u] + a.c_L * dt * L;
-            if (a.base) o += a.c_base * ba[u];
-            if (a.out2) a.out2[gi] = a.d_cur * cu[u] + a.d_L * dt * L + (a.x2 ? a.d_x2 * x2[u] : 0.0);
-            a.out[gi] = o;
-            if (!isfinite(o)) bad |= 2;
+            if (i < nel && gi < gend) combine(i, gi, cu[u], ba[u], x2[u]);
         }
     }
     if (bad) atomicOr(blkflag, bad);
