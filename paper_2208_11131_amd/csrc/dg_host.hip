@@ -400,19 +400,22 @@ void get_kernels(int dim, int prec, int P, int phys, KernelSet *k)
 }
 
 // Fixed-tile volume kernel of the tuned table for this tile, if one was built.
-const void *get_vol_fixed(int dim, int prec, int P, int phys, int C, int NT, int forced)
+const void *get_vol_fixed(int dim, int prec, int P, int phys, int C, int NT, int forced, int batched = 0)
 {
     if (dim == 2)
-        return (prec == DG_PREC_FP64 ? dgk::dgk_vol_fixed_2d_f64 : dgk::dgk_vol_fixed_2d_f32)(P, phys, C, NT, forced);
-    return (prec == DG_PREC_FP64 ? dgk::dgk_vol_fixed_3d_f64 : dgk::dgk_vol_fixed_3d_f32)(P, phys, C, NT, forced);
+        return (prec == DG_PREC_FP64 ? dgk::dgk_vol_fixed_2d_f64 : dgk::dgk_vol_fixed_2d_f32)(P, phys, C, NT, forced,
+                                                                                              batched);
+    return (prec == DG_PREC_FP64 ? dgk::dgk_vol_fixed_3d_f64 : dgk::dgk_vol_fixed_3d_f32)(P, phys, C, NT, forced,
+                                                                                          batched);
 }
 
 // Fixed-tile face kernel of the tuned table for this tile, if one was built.
-const void *get_face_fixed(int dim, int prec, int P, int phys, int C, int NT)
+const void *get_face_fixed(int dim, int prec, int P, int phys, int C, int NT, int batched = 0)
 {
     if (dim == 2)
-        return (prec == DG_PREC_FP64 ? dgk::dgk_face_fixed_2d_f64 : dgk::dgk_face_fixed_2d_f32)(P, phys, C, NT);
-    return (prec == DG_PREC_FP64 ? dgk::dgk_face_fixed_3d_f64 : dgk::dgk_face_fixed_3d_f32)(P, phys, C, NT);
+        return (prec == DG_PREC_FP64 ? dgk::dgk_face_fixed_2d_f64 : dgk::dgk_face_fixed_2d_f32)(P, phys, C, NT,
+                                                                                                batched);
+    return (prec == DG_PREC_FP64 ? dgk::dgk_face_fixed_3d_f64 : dgk::dgk_face_fixed_3d_f32)(P, phys, C, NT, batched);
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
@@ -1154,11 +1157,21 @@ dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, doub
         g.face_lds = c0->face_lds;
         g.cfl_lds = c0->cfl_lds;
         g.stages = c0->stages;
+        // fixed-tile grouped kernels when the (common) tile has one
+        {
+            const void *vf = get_vol_fixed(c0->dim, c0->precision, P, c0->phys, c0->vol_C, c0->vol_T, 0, 1);
+            const void *ff = get_face_fixed(c0->dim, c0->precision, P, c0->phys, c0->face_C, c0->face_T, 1);
+            if (vf) g.ks.vol_b = vf;
+            if (ff) g.ks.face_b = ff;
+        }
         if (!g.ks.vol_b || !g.ks.face_b || !g.ks64.cfl_b) {
             batch_release(b);
             delete b;
             return DG_EUNSUPPORTED;
         }
+        (void)hipFuncSetAttribute(g.ks.vol_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+        (void)hipFuncSetAttribute(g.ks.face_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+        (void)hipFuncSetAttribute(g.ks64.cfl_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
         for (int i : g.boxes) {
             const dg_ctx *c = b->box[i];
             dgk::BoxDesc d;

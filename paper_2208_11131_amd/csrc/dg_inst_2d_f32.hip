@@ -47,14 +47,14 @@ void dgk_get_2d_f32(int P, int ph, KernelSet *k)
     }
 }
 
-const void *dgk_vol_fixed_2d_f32(int order, int phys, int C, int NT, int forced)
+const void *dgk_vol_fixed_2d_f32(int order, int phys, int C, int NT, int forced, int batched)
 {
-    return find_fixed_vol<2, 1, float>(order, phys, C, NT, forced, std::make_index_sequence<kNumTiles>{});
+    return find_fixed_vol<2, 1, float>(order, phys, C, NT, forced, batched, std::make_index_sequence<kNumTiles>{});
 }
 
-const void *dgk_face_fixed_2d_f32(int order, int phys, int C, int NT)
+const void *dgk_face_fixed_2d_f32(int order, int phys, int C, int NT, int batched)
 {
-    return find_fixed_face<2, 1, float>(order, phys, C, NT, std::make_index_sequence<kNumTiles>{});
+    return find_fixed_face<2, 1, float>(order, phys, C, NT, batched, std::make_index_sequence<kNumTiles>{});
 }
 
 int dgk_upload_2d_f32(const Tab<double> *d, const Tab<float> *f)

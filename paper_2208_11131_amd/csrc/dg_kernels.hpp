@@ -642,8 +642,8 @@ __device__ __forceinline__ int owner_box(const BoxDesc *boxes, int nbox, long lo
 
 // Grouped face kernel: every box of one (dim, order) group; flat block index
 // -> (box, direction, pencil).
-template <int D, int P, typename T, int PH>
-__global__ void __launch_bounds__(512) face_kernel_batched(const BoxDesc *boxes, int nbox, int stage_cur)
+template <int D, int P, typename T, int PH, int CC, int NTC>
+__device__ __forceinline__ void face_batched_body(const BoxDesc *boxes, int nbox, int stage_cur)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const long long b = xcd_block(blockIdx.x, gridDim.x);
@@ -654,16 +654,31 @@ __global__ void __launch_bounds__(512) face_kernel_batched(const BoxDesc *boxes,
     a.w = boxes[i].reg[stage_cur];
     a.fb = boxes[i].fb;
     a.faces_per_block = boxes[i].faces_per_block;
+    if (CC > 0 && a.faces_per_block != CC) return;   // host selection error
     long long loc = b - boxes[i].start[1];
     for (int ax = 0; ax < D; ++ax) {
         const long long n = pencils(geo, ax, a.faces_per_block);
         if (loc < n) {
-            face_dispatch<D, P, T, PH>(ph, geo, a, smem, ax, loc);
+            face_dispatch<D, P, T, PH, CC, NTC>(ph, geo, a, smem, ax, loc);
             return;
         }
         loc -= n;
     }
 }
+
+template <int D, int P, typename T, int PH>
+__global__ void __launch_bounds__(512) face_kernel_batched(const BoxDesc *boxes, int nbox, int stage_cur)
+{
+    face_batched_body<D, P, T, PH, 0, 0>(boxes, nbox, stage_cur);
+}
+
+// Grouped face kernel with the pencil length C and block size NT fixed.
+template <int D, int P, typename T, int PH, int C, int NT>
+__global__ void __launch_bounds__(NT) face_kernel_batched_fixed(const BoxDesc *boxes, int nbox, int stage_cur)
+{
+    face_batched_body<D, P, T, PH, C, NT>(boxes, nbox, stage_cur);
+}
+
 
 // LDS bytes of the face kernel for pencils of C faces: slot indices, the C+1
 // cells' coefficients W overlaid by a scratch of 5 C F p^(d-1) (W is dead
@@ -1106,8 +1121,10 @@ __global__ void __launch_bounds__(NT) vol_kernel_fixed(Phys ph, Geo geo, VolArgs
 }
 
 // Grouped volume/stage kernel over every box of one (dim, order) group.
-template <int D, int P, typename T, int PH>
-__global__ void __launch_bounds__(512) vol_kernel_batched(const BoxDesc *boxes, int nbox, StageDesc sd)
+// Body of the grouped volume kernel; CC / NTC as in vol_body (0 = from the
+// launch).  Ensembles carry no forcing.
+template <int D, int P, typename T, int PH, int CC, int NTC>
+__device__ __forceinline__ void vol_batched_body(const BoxDesc *boxes, int nbox, const StageDesc &sd)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const long long b = xcd_block(blockIdx.x, gridDim.x);
@@ -1136,7 +1153,22 @@ __global__ void __launch_bounds__(512) vol_kernel_batched(const BoxDesc *boxes, 
     a.flag = B.flag;
     a.check = 1;
     a.cells_per_block = B.cells_per_block;
-    vol_body<D, P, T, PH>(ph, geo, a, smem, b - B.start[0]);
+    if (CC > 0 && B.cells_per_block != CC) return;   // host selection error
+    vol_body<D, P, T, PH, CC, NTC, (CC > 0 ? 0 : -1)>(ph, geo, a, smem, b - B.start[0]);
+}
+
+template <int D, int P, typename T, int PH>
+__global__ void __launch_bounds__(512) vol_kernel_batched(const BoxDesc *boxes, int nbox, StageDesc sd)
+{
+    vol_batched_body<D, P, T, PH, 0, 0>(boxes, nbox, sd);
+}
+
+// Grouped volume kernel with the tile fixed at compile time (every box of the
+// group has cells_per_block == C; block size NT).
+template <int D, int P, typename T, int PH, int C, int NT>
+__global__ void __launch_bounds__(NT) vol_kernel_batched_fixed(const BoxDesc *boxes, int nbox, StageDesc sd)
+{
+    vol_batched_body<D, P, T, PH, C, NT>(boxes, nbox, sd);
 }
 
 template <int D, int P, typename T, int PH>
@@ -1256,9 +1288,11 @@ FixedVol fixed_vol_entry()
     if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 2 &&
                   e.vol_C > 0 && e.vol_T >= 64 && e.vol_T <= 512 && e.vol_T % 64 == 0 && (FO == 0 || DIM == 3))
         return FixedVol{e.order, e.phys, e.vol_C, e.vol_T, FO,
-                        (const void *)&vol_kernel_fixed<DIM, e.order, T, e.phys, e.vol_C, e.vol_T, FO>};
+                        (const void *)&vol_kernel_fixed<DIM, e.order, T, e.phys, e.vol_C, e.vol_T, FO>,
+                        FO == 0 ? (const void *)&vol_kernel_batched_fixed<DIM, e.order, T, e.phys, e.vol_C, e.vol_T>
+                                : nullptr};
     else
-        return FixedVol{0, 0, 0, 0, 0, nullptr};
+        return FixedVol{0, 0, 0, 0, 0, nullptr, nullptr};
 }
 
 // Entry I of the tuned table as a fixed-tile face kernel, or an empty record.
@@ -1269,27 +1303,30 @@ FixedVol fixed_face_entry()
     if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 2 &&
                   e.face_C > 0 && e.face_T >= 64 && e.face_T <= 512 && e.face_T % 64 == 0)
         return FixedVol{e.order, e.phys, e.face_C, e.face_T, 0,
-                        (const void *)&face_kernel_fixed<DIM, e.order, T, e.phys, e.face_C, e.face_T>};
+                        (const void *)&face_kernel_fixed<DIM, e.order, T, e.phys, e.face_C, e.face_T>,
+                        (const void *)&face_kernel_batched_fixed<DIM, e.order, T, e.phys, e.face_C, e.face_T>};
     else
-        return FixedVol{0, 0, 0, 0, 0, nullptr};
+        return FixedVol{0, 0, 0, 0, 0, nullptr, nullptr};
 }
 
 template <int DIM, int PREC, typename T, size_t... I>
-const void *find_fixed_face(int order, int phys, int C, int NT, std::index_sequence<I...>)
+const void *find_fixed_face(int order, int phys, int C, int NT, int batched, std::index_sequence<I...>)
 {
-    static const FixedVol tab[] = {fixed_face_entry<DIM, PREC, T, I>()..., FixedVol{0, 0, 0, 0, 0, nullptr}};
+    static const FixedVol tab[] = {fixed_face_entry<DIM, PREC, T, I>()..., FixedVol{0, 0, 0, 0, 0, nullptr, nullptr}};
     for (const FixedVol &f : tab)
-        if (f.fn && f.order == order && f.phys == phys && f.C == C && f.NT == NT) return f.fn;
+        if (f.fn && f.order == order && f.phys == phys && f.C == C && f.NT == NT) return batched ? f.fnb : f.fn;
     return nullptr;
 }
 
 template <int DIM, int PREC, typename T, size_t... I>
-const void *find_fixed_vol(int order, int phys, int C, int NT, int forced, std::index_sequence<I...>)
+const void *find_fixed_vol(int order, int phys, int C, int NT, int forced, int batched,
+                           std::index_sequence<I...>)
 {
     static const FixedVol tab[] = {fixed_vol_entry<DIM, PREC, T, I, 0>()...,
-                                   fixed_vol_entry<DIM, PREC, T, I, 1>()..., FixedVol{0, 0, 0, 0, 0, nullptr}};
+                                   fixed_vol_entry<DIM, PREC, T, I, 1>()..., FixedVol{0, 0, 0, 0, 0, nullptr, nullptr}};
     for (const FixedVol &f : tab)
-        if (f.fn && f.order == order && f.phys == phys && f.C == C && f.NT == NT && f.forced == forced) return f.fn;
+        if (f.fn && f.order == order && f.phys == phys && f.C == C && f.NT == NT && f.forced == forced)
+            return batched ? f.fnb : f.fn;
     return nullptr;
 }
 

@@ -26,16 +26,17 @@ void dgk_get_3d_f64(int P, int ph, KernelSet *k);
 void dgk_get_2d_f32(int P, int ph, KernelSet *k);
 void dgk_get_3d_f32(int P, int ph, KernelSet *k);
 // Fixed-tile volume kernel for (order, physics, cells per block, threads,
-// forcing) if the tuned table has one for this unit, else null.
-const void *dgk_vol_fixed_2d_f64(int order, int phys, int C, int NT, int forced);
-const void *dgk_vol_fixed_3d_f64(int order, int phys, int C, int NT, int forced);
-const void *dgk_vol_fixed_2d_f32(int order, int phys, int C, int NT, int forced);
-const void *dgk_vol_fixed_3d_f32(int order, int phys, int C, int NT, int forced);
+// forcing) if the tuned table has one for this unit, else null; batched = 1
+// selects the grouped (ensemble) variant.
+const void *dgk_vol_fixed_2d_f64(int order, int phys, int C, int NT, int forced, int batched);
+const void *dgk_vol_fixed_3d_f64(int order, int phys, int C, int NT, int forced, int batched);
+const void *dgk_vol_fixed_2d_f32(int order, int phys, int C, int NT, int forced, int batched);
+const void *dgk_vol_fixed_3d_f32(int order, int phys, int C, int NT, int forced, int batched);
 // Fixed-tile face kernel for (order, physics, faces per pencil, threads).
-const void *dgk_face_fixed_2d_f64(int order, int phys, int C, int NT);
-const void *dgk_face_fixed_3d_f64(int order, int phys, int C, int NT);
-const void *dgk_face_fixed_2d_f32(int order, int phys, int C, int NT);
-const void *dgk_face_fixed_3d_f32(int order, int phys, int C, int NT);
+const void *dgk_face_fixed_2d_f64(int order, int phys, int C, int NT, int batched);
+const void *dgk_face_fixed_3d_f64(int order, int phys, int C, int NT, int batched);
+const void *dgk_face_fixed_2d_f32(int order, int phys, int C, int NT, int batched);
+const void *dgk_face_fixed_3d_f32(int order, int phys, int C, int NT, int batched);
 int dgk_upload_2d_f64(const Tab<double> *d, const Tab<float> *f);
 int dgk_upload_3d_f64(const Tab<double> *d, const Tab<float> *f);
 int dgk_upload_2d_f32(const Tab<double> *d, const Tab<float> *f);

@@ -17,10 +17,12 @@ constexpr TileEntry kTiles[] = {
 
 constexpr size_t kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]) - 1;
 
-// Fixed-tile volume or face kernel of one table entry (host stub), or null.
+// Fixed-tile volume or face kernel of one table entry (host stubs of the
+// single-box and the grouped variant), or null.
 struct FixedVol {
     int order, phys, C, NT, forced;
     const void *fn;
+    const void *fnb;
 };
 
 }  // namespace dgk
