@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -873,9 +874,12 @@ size_t dg_state_len(const dg_ctx *c) { return c ? (size_t)c->ncells * c->F * c->
 
 int dg_num_fields(const dg_ctx *c) { return c ? c->F : 0; }
 
+// The kernels move the state in 16-byte groups.
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 dg_status dg_rhs(dg_ctx *c, const double *w, double *wdot, void *stream)
 {
-    if (!c || !w || !wdot || w == wdot) return DG_EINVAL;
+    if (!c || !w || !wdot || w == wdot || !aligned16(w) || !aligned16(wdot)) return DG_EINVAL;
     dgk::VolArgs v = blank_args();
     v.cur = w;
     v.out = wdot;
@@ -888,13 +892,13 @@ dg_status dg_rhs(dg_ctx *c, const double *w, double *wdot, void *stream)
 
 dg_status dg_step(dg_ctx *c, double *w, double dt, void *stream)
 {
-    if (!c || !w || !(dt > 0.0) || !std::isfinite(dt)) return DG_EINVAL;
+    if (!c || !w || !aligned16(w) || !(dt > 0.0) || !std::isfinite(dt)) return DG_EINVAL;
     return rk_step(c, w, dt, nullptr, (hipStream_t)stream);
 }
 
 dg_status dg_step_cfl(dg_ctx *c, double *w, double *dt_dev, void *stream)
 {
-    if (!c || !w) return DG_EINVAL;
+    if (!c || !w || !aligned16(w)) return DG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     dg_status st = run_cfl(c, w, dt_dev, s);
     if (st != DG_OK) return st;
@@ -1226,7 +1230,7 @@ dg_status dg_batch_step(dg_batch *b, double *const *w, int use_graph, void *stre
 {
     if (!b || !w) return DG_EINVAL;
     for (int i = 0; i < b->nbox; ++i)
-        if (!w[i]) return DG_EINVAL;
+        if (!w[i] || !aligned16(w[i])) return DG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     bool changed = false;
     for (int i = 0; i < b->nbox; ++i)

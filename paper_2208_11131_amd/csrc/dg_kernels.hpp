@@ -213,6 +213,46 @@ __device__ __forceinline__ void line_pass_pad(const T *__restrict__ in, T *__res
     }
 }
 
+// VW consecutive doubles moved by one global access (VW = 2: 16-byte loads
+// and stores; the state arrays are 16-byte aligned and a group never
+// straddles a field or a cell when the per-cell length is even).
+template <int VW>
+struct DV {
+    double x[VW];
+};
+
+template <int VW>
+__device__ __forceinline__ DV<VW> ldv(const double *p)
+{
+    DV<VW> r;
+    if constexpr (VW == 2) {
+        const double2 t = *(const double2 *)p;
+        r.x[0] = t.x;
+        r.x[1] = t.y;
+    } else {
+        r.x[0] = *p;
+    }
+    return r;
+}
+
+template <int VW>
+__device__ __forceinline__ void stv(double *p, const DV<VW> &v)
+{
+    if constexpr (VW == 2)
+        *(double2 *)p = make_double2(v.x[0], v.x[1]);
+    else
+        *p = v.x[0];
+}
+
+template <int VW>
+__device__ __forceinline__ DV<VW> zdv()
+{
+    DV<VW> r;
+#pragma unroll
+    for (int h = 0; h < VW; ++h) r.x[h] = 0.0;
+    return r;
+}
+
 // Fields per physics variant: PH = 0 Euler, 1 Navier-Stokes, 2 artificial
 // viscosity (alpha field; Navier-Stokes terms switched at run time).
 template <int D, int PH>
@@ -437,23 +477,28 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     }
     __syncthreads();
     constexpr int UNR = 4;      // loads in flight per thread
-    for (int i0 = tid; i0 < (C + 1) * FNP; i0 += UNR * nt) {
-        double v[UNR];
+    constexpr int VW = (FNP % 2 == 0) ? 2 : 1;   // doubles per global access
+    const int ngrp = (C + 1) * FNP / VW;
+    for (int i0 = tid; i0 < ngrp; i0 += UNR * nt) {
+        DV<VW> v[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const int i = i0 + u * nt;
-            const int sl = i < (C + 1) * FNP ? i / FNP : 0;
-            v[u] = i < (C + 1) * FNP ? a.w[cellidx[sl] * FNP + (i - sl * FNP)] : 0.0;
+            const int i = (i0 + u * nt) * VW;
+            const int sl = i0 + u * nt < ngrp ? i / FNP : 0;
+            v[u] = i0 + u * nt < ngrp ? ldv<VW>(a.w + cellidx[sl] * FNP + (i - sl * FNP)) : zdv<VW>();
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const int i = i0 + u * nt;
-            if (i < (C + 1) * FNP) {
-                const int sl = i / FNP, e = i - sl * FNP;
-                const int f = e / NP, j = e - f * NP;
-                double x = v[u];
-                if (mir[sl] && ((j / S) % P) & 1) x = -x;
-                W[(sl * F + f) * NAP + ppos<P>(j)] = (T)x;
+            if (i0 + u * nt < ngrp) {
+#pragma unroll
+                for (int h = 0; h < VW; ++h) {
+                    const int i = (i0 + u * nt) * VW + h;
+                    const int sl = i / FNP, e = i - sl * FNP;
+                    const int f = e / NP, j = e - f * NP;
+                    double x = v[u].x[h];
+                    if (mir[sl] && ((j / S) % P) & 1) x = -x;
+                    W[(sl * F + f) * NAP + ppos<P>(j)] = (T)x;
+                }
             }
         }
     }
@@ -742,23 +787,28 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     // 1. load the tile's weights (and forcing coefficients); per-cell data.
     //    UNR loads per thread are issued before their LDS stores.
     constexpr int UNR = 4;
+    constexpr int VW = (FNP % 2 == 0) ? 2 : 1;   // doubles per global access
     const long long gbase = c0 * FNP, gend = NC * FNP;
-    for (int i0 = tid; i0 < C * FNP; i0 += UNR * nt) {
-        double v[UNR];
+    const int ngrp = C * FNP / VW;
+    for (int i0 = tid; i0 < ngrp; i0 += UNR * nt) {
+        DV<VW> v[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const int i = i0 + u * nt;
-            long long gi = gbase + i;
-            if (gi >= gend) gi = (NC - 1) * FNP + i % FNP;
-            v[u] = (i < C * FNP) ? a.cur[gi] : 0.0;
+            const int e = (i0 + u * nt) * VW;
+            long long gi = gbase + e;
+            if (gi >= gend) gi = (NC - 1) * FNP + e % FNP;   // tail cells: copies of the last cell
+            v[u] = (i0 + u * nt < ngrp) ? ldv<VW>(a.cur + gi) : zdv<VW>();
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const int i = i0 + u * nt;
-            if (i < C * FNP) {
-                const int c = i / FNP, r = i - c * FNP;
-                const int f = r / NP, j = r - f * NP;
-                X0[f * CNP + c * NAP + ppos<P>(j)] = (T)v[u];
+            if (i0 + u * nt < ngrp) {
+#pragma unroll
+                for (int h = 0; h < VW; ++h) {
+                    const int i = (i0 + u * nt) * VW + h;
+                    const int c = i / FNP, r = i - c * FNP;
+                    const int f = r / NP, j = r - f * NP;
+                    X0[f * CNP + c * NAP + ppos<P>(j)] = (T)v[u].x[h];
+                }
             }
         }
     }
@@ -934,10 +984,9 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     // RK inputs of the first NLD elements of each thread (the rest, if any,
     // are read where they are used).  With a fixed tile both counts are exact.
     constexpr int NLF = (CC > 0 && NTC > 0) ? (CC * Fc * K + NTC - 1) / NTC : 1;
-    constexpr int NLD0 = (CC > 0 && NTC > 0) ? (CC * FNP + NTC - 1) / NTC : 2;
+    constexpr int NLD0 = (CC > 0 && NTC > 0) ? (CC * FNP / VW + NTC - 1) / NTC : 2;
     constexpr int NLD = NLD0 < 8 ? NLD0 : 8;
     const int nlift = C * Fc * K;
-    const int nel = C * FNP;
     auto lift_load = [&](int q, T *Fl, T *Fu) {
         const bool act = q < nlift;
         const int c = act ? q / (Fc * K) : 0;
@@ -965,15 +1014,15 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     }
 
     const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
-    double pc[NLD], pb[NLD], px[NLD];
+    DV<VW> pc[NLD], pb[NLD], px[NLD];
 #pragma unroll
     for (int m = 0; m < NLD; ++m) {
-        const int i = tid + m * nt;
-        const long long gi = gbase + i;
-        const bool ok = i < nel && gi < gend;
-        pc[m] = ok ? a.cur[gi] : 0.0;
-        pb[m] = (ok && a.base) ? a.base[gi] : 0.0;
-        px[m] = (ok && a.x2) ? a.x2[gi] : 0.0;
+        const int g = tid + m * nt;
+        const long long gi = gbase + (long long)g * VW;
+        const bool ok = g < ngrp && gi < gend;
+        pc[m] = ok ? ldv<VW>(a.cur + gi) : zdv<VW>();
+        pb[m] = (ok && a.base) ? ldv<VW>(a.base + gi) : zdv<VW>();
+        px[m] = (ok && a.x2) ? ldv<VW>(a.x2 + gi) : zdv<VW>();
     }
 
     // 6. surface lift in point space: Q(i, k) += L_i(-1) F_lower(k) - L_i(+1) F_upper(k),
@@ -1019,40 +1068,46 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     }
     const T *V = (D == 3) ? Wk : U;
 
-    // 8. RK combination in FP64 and write-back
+    // 8. RK combination in FP64 and write-back, VW consecutive weights per access
     const double pref = ph.pref;
     int bad = 0;
-    auto combine = [&](int i, long long gi, double cu, double ba, double x2) {
-        const int c = i / FNP, r = i - c * FNP;
-        const int f = r / NP, j = r - f * NP;
-        const double L = pref * (double)V[f * CNP + c * NAP + ppos<P>(j)];
-        double o = a.c_cur * cu + a.c_L * dt * L;
-        if (a.base) o += a.c_base * ba;
-        if (a.out2) a.out2[gi] = a.d_cur * cu + a.d_L * dt * L + (a.x2 ? a.d_x2 * x2 : 0.0);
-        a.out[gi] = o;
-        if (!isfinite(o)) bad |= 2;
+    auto combine = [&](int g, long long gi, const DV<VW> &cu, const DV<VW> &ba, const DV<VW> &x2) {
+        DV<VW> o, o2;
+#pragma unroll
+        for (int h = 0; h < VW; ++h) {
+            const int i = g * VW + h;
+            const int c = i / FNP, r = i - c * FNP;
+            const int f = r / NP, j = r - f * NP;
+            const double L = pref * (double)V[f * CNP + c * NAP + ppos<P>(j)];
+            o.x[h] = a.c_cur * cu.x[h] + a.c_L * dt * L;
+            if (a.base) o.x[h] += a.c_base * ba.x[h];
+            o2.x[h] = a.d_cur * cu.x[h] + a.d_L * dt * L + (a.x2 ? a.d_x2 * x2.x[h] : 0.0);
+            if (!isfinite(o.x[h])) bad |= 2;
+        }
+        if (a.out2) stv<VW>(a.out2 + gi, o2);
+        stv<VW>(a.out + gi, o);
     };
 #pragma unroll
     for (int m = 0; m < NLD; ++m) {
-        const int i = tid + m * nt;
-        const long long gi = gbase + i;
-        if (i < nel && gi < gend) combine(i, gi, pc[m], pb[m], px[m]);
+        const int g = tid + m * nt;
+        const long long gi = gbase + (long long)g * VW;
+        if (g < ngrp && gi < gend) combine(g, gi, pc[m], pb[m], px[m]);
     }
-    for (int i0 = tid + NLD * nt; i0 < nel; i0 += UNR * nt) {
-        double cu[UNR], ba[UNR], x2[UNR];
+    for (int i0 = tid + NLD * nt; i0 < ngrp; i0 += UNR * nt) {
+        DV<VW> cu[UNR], ba[UNR], x2[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const long long gi = gbase + i0 + u * nt;
-            const bool ok = (i0 + u * nt < nel) && gi < gend;
-            cu[u] = ok ? a.cur[gi] : 0.0;
-            ba[u] = (ok && a.base) ? a.base[gi] : 0.0;
-            x2[u] = (ok && a.x2) ? a.x2[gi] : 0.0;
+            const long long gi = gbase + (long long)(i0 + u * nt) * VW;
+            const bool ok = (i0 + u * nt < ngrp) && gi < gend;
+            cu[u] = ok ? ldv<VW>(a.cur + gi) : zdv<VW>();
+            ba[u] = (ok && a.base) ? ldv<VW>(a.base + gi) : zdv<VW>();
+            x2[u] = (ok && a.x2) ? ldv<VW>(a.x2 + gi) : zdv<VW>();
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const int i = i0 + u * nt;
-            const long long gi = gbase + i;
-            if (i < nel && gi < gend) combine(i, gi, cu[u], ba[u], x2[u]);
+            const int g = i0 + u * nt;
+            const long long gi = gbase + (long long)g * VW;
+            if (g < ngrp && gi < gend) combine(g, gi, cu[u], ba[u], x2[u]);
         }
     }
     if (bad) atomicOr(blkflag, bad);

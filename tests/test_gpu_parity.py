@@ -330,6 +330,15 @@ def test_error_flags():
         gpu.step(torch.zeros(5, dtype=torch.float64, device="cuda"), 1e-3)
     with pytest.raises(dg.DgError):
         gpu.step(w, -1.0)
+    # a state view 8 bytes off a 16-byte boundary is refused before any launch
+    buf = torch.zeros(w.numel() + 1, dtype=torch.float64, device="cuda")
+    off = buf[1:].view(w.shape)
+    assert off.data_ptr() % 16 == 8
+    for call in (lambda: gpu.step(off, 1e-6), lambda: gpu.step_cfl(off), lambda: gpu.rhs(off),
+                 lambda: gpu.rhs(w, out=off)):
+        with pytest.raises(dg.DgError):
+            call()
+    assert float(buf.abs().sum()) == 0.0
 
 
 def _sampled_cells(ncells, nsample, rng):
