@@ -17,7 +17,7 @@
  *     w_0 of each field is the cell mean (orthonormal basis, Sec. 2.2).
  *   - Every pointer argument named w, wdot, s_coeffs or R is a DEVICE pointer
  *     owned by the caller (e.g. a torch tensor), 8-byte aligned; w and wdot
- *     of dg_rhs / dg_step / dg_step_cfl / dg_batch_step must be 16-byte
+ *     of dg_rhs / dg_step / dg_step_cfl / dg_max_dt / dg_batch_step must be 16-byte
  *     aligned (the state is moved in 16-byte groups; DG_EINVAL otherwise,
  *     torch and hipMalloc allocations are 256-byte aligned); `stream` is a
  *     hipStream_t passed as void* (NULL = default stream).  Calls enqueue work

@@ -210,63 +210,71 @@ dg_status ensure_tables(int dev)
 
 __device__ __forceinline__ double nanmax2(double a, double b) { return (b > a || b != b) ? b : a; }
 
-// Reduce the per-block maxima of the CFL kernel (one block of 256 threads,
-// fixed order) and form dt = f_CFL h / (2 p (c_max + v_max)).
-__global__ void cfl_finalize(const double *part, int nblk, double *res, double *dt_copy, double num)
+// Maxima of the (c_s, |v|) pairs part[0 .. nblk) with one block of
+// kFinT threads: each pair is one 16-byte load, four independent
+// accumulators per thread keep four loads in flight, then a tree in LDS.
+// Max is order independent, so the result does not depend on the split.
+constexpr int kFinT = 1024;
+
+__device__ __forceinline__ void cfl_reduce_pairs(const double *part, long long nblk, double *cm, double *vm)
 {
-    __shared__ double rc[256], rv[256];
+    __shared__ double rc[kFinT], rv[kFinT];
     const int t = threadIdx.x;
-    double c = 0.0, v = 0.0;
-    for (int b = t; b < nblk; b += blockDim.x) {
-        c = nanmax2(c, part[2 * b]);
-        v = nanmax2(v, part[2 * b + 1]);
+    const double2 *pp = (const double2 *)part;
+    double c[4] = {0.0, 0.0, 0.0, 0.0}, v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long b0 = t; b0 < nblk; b0 += 4 * kFinT) {
+        double2 x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long long b = b0 + (long long)u * kFinT;
+            x[u] = b < nblk ? pp[b] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = nanmax2(c[u], x[u].x);
+            v[u] = nanmax2(v[u], x[u].y);
+        }
     }
-    rc[t] = c;
-    rv[t] = v;
+    rc[t] = nanmax2(nanmax2(c[0], c[1]), nanmax2(c[2], c[3]));
+    rv[t] = nanmax2(nanmax2(v[0], v[1]), nanmax2(v[2], v[3]));
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) {
-            rc[t] = nanmax2(rc[t], rc[t + s]);
-            rv[t] = nanmax2(rv[t], rv[t + s]);
+    for (int st = kFinT / 2; st > 0; st >>= 1) {
+        if (t < st) {
+            rc[t] = nanmax2(rc[t], rc[t + st]);
+            rv[t] = nanmax2(rv[t], rv[t + st]);
         }
         __syncthreads();
     }
-    if (t == 0) {
-        const double dt = num / (rc[0] + rv[0]);
+    *cm = rc[0];
+    *vm = rv[0];
+}
+
+// dt = f_CFL h / (2 p (c_max + v_max)) from the CFL kernel's partial maxima.
+__global__ void __launch_bounds__(kFinT) cfl_finalize(const double *part, int nblk, double *res, double *dt_copy,
+                                                      double num)
+{
+    double cm, vm;
+    cfl_reduce_pairs(part, nblk, &cm, &vm);
+    if (threadIdx.x == 0) {
+        const double dt = num / (cm + vm);
         res[0] = dt;
-        res[1] = rc[0];
-        res[2] = rv[0];
+        res[1] = cm;
+        res[2] = vm;
         if (dt_copy) dt_copy[0] = dt;
     }
 }
 
 // Per-box CFL reduction of a grouped launch: block i reduces box i's partials.
-__global__ void cfl_finalize_batched(const dgk::BoxDesc *boxes, double cfl)
+__global__ void __launch_bounds__(kFinT) cfl_finalize_batched(const dgk::BoxDesc *boxes, double cfl)
 {
-    __shared__ double rc[256], rv[256];
     const dgk::BoxDesc &B = boxes[blockIdx.x];
-    const int t = threadIdx.x;
-    const long long nb = B.nblocks[2];
-    double c = 0.0, v = 0.0;
-    for (long long k = t; k < nb; k += blockDim.x) {
-        c = nanmax2(c, B.cfl_part[2 * k]);
-        v = nanmax2(v, B.cfl_part[2 * k + 1]);
-    }
-    rc[t] = c;
-    rv[t] = v;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) {
-            rc[t] = nanmax2(rc[t], rc[t + s]);
-            rv[t] = nanmax2(rv[t], rv[t + s]);
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
+    double cm, vm;
+    cfl_reduce_pairs(B.cfl_part, B.nblocks[2], &cm, &vm);
+    if (threadIdx.x == 0) {
         const double num = cfl * B.ph.h / (2.0 * B.ph.order);
-        B.dt[0] = num / (rc[0] + rv[0]);
-        B.dt[1] = rc[0];
-        B.dt[2] = rv[0];
+        B.dt[0] = num / (cm + vm);
+        B.dt[1] = cm;
+        B.dt[2] = vm;
     }
 }
 
@@ -496,7 +504,7 @@ dg_status run_cfl(dg_ctx *c, const double *w, double *dt_copy, hipStream_t s)
     int nblk = c->cfl_blocks;
     double *res = c->scal;
     void *fargs[] = {&part, &nblk, &res, &dt_copy, &num};
-    return launch(c, 3, (const void *)&cfl_finalize, dim3(1), dim3(256), fargs, 0, s);
+    return launch(c, 3, (const void *)&cfl_finalize, dim3(1), dim3(kFinT), fargs, 0, s);
 }
 
 // SSP-RK step in Shu-Osher form; dt from the host value or a device pointer.
@@ -907,7 +915,7 @@ dg_status dg_step_cfl(dg_ctx *c, double *w, double *dt_dev, void *stream)
 
 dg_status dg_max_dt(dg_ctx *c, const double *w, double *dt_out, double *cmax_out, double *vmax_out, void *stream)
 {
-    if (!c || !w || !dt_out) return DG_EINVAL;
+    if (!c || !w || !aligned16(w) || !dt_out) return DG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     dg_status st = run_cfl(c, w, nullptr, s);
     if (st != DG_OK) return st;
@@ -1099,7 +1107,7 @@ dg_status batch_enqueue(dg_batch *b, hipStream_t s)
         {
             double cfl = b->cfl;
             void *args[] = {&d, &cfl};
-            if (!ok(hipLaunchKernel((const void *)&cfl_finalize_batched, dim3(n), dim3(256), args, 0, s)))
+            if (!ok(hipLaunchKernel((const void *)&cfl_finalize_batched, dim3(n), dim3(kFinT), args, 0, s)))
                 return DG_EDEVICE;
         }
         dgk::StageDesc sd[5];

@@ -1255,11 +1255,16 @@ __device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const C
     double *X0 = (double *)smem;
     double *X1 = X0 + C * Fc * NP;
     double *red = X1 + C * Fc * NP;      // [2][nt]
-    for (int i = tid; i < C * Fc * NP; i += nt) {
+    // the first Fc fields of each cell, VW consecutive weights per access
+    constexpr int VW = ((Fc * NP) % 2 == 0 && FNP % 2 == 0) ? 2 : 1;
+    for (int g = tid; g < C * Fc * NP / VW; g += nt) {
+        const int i = g * VW;
         const int c = i / (Fc * NP), r = i - c * (Fc * NP);
         long long cc = c0 + c;
         if (cc >= NC) cc = NC - 1;
-        X0[i] = a.w[cc * FNP + r];
+        const DV<VW> v = ldv<VW>(a.w + cc * FNP + r);
+#pragma unroll
+        for (int h = 0; h < VW; ++h) X0[i + h] = v.x[h];
     }
     __syncthreads();
     axis_pass<P, D, 0, double, M_B, false, Fc>(X0, Fc * NP, X1, Fc * NP, C);

@@ -335,7 +335,7 @@ def test_error_flags():
     off = buf[1:].view(w.shape)
     assert off.data_ptr() % 16 == 8
     for call in (lambda: gpu.step(off, 1e-6), lambda: gpu.step_cfl(off), lambda: gpu.rhs(off),
-                 lambda: gpu.rhs(w, out=off)):
+                 lambda: gpu.rhs(w, out=off), lambda: gpu.max_dt(off)):
         with pytest.raises(dg.DgError):
             call()
     assert float(buf.abs().sum()) == 0.0
