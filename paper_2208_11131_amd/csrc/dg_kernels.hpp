@@ -124,19 +124,28 @@ struct Pad {
     static constexpr int PP = (P % 2 == 0) ? P + 1 : P;
 };
 
+// Row pitch of the face kernel's arrays: unpadded at p = 4, where that
+// measured faster (the face kernel's lines are short and its LDS footprint
+// per pencil sets the occupancy), padded like the volume kernel otherwise.
 template <int P>
+struct FacePad {
+    static constexpr int PP = (P == 4) ? P : Pad<P>::PP;
+};
+
+// Position of point j in a per-cell array with row pitch RP.
+template <int P, int RP = Pad<P>::PP>
 __device__ __forceinline__ int ppos(int j)
 {
-    return (j % P) + Pad<P>::PP * (j / P);
+    return (j % P) + RP * (j / P);
 }
 
 // line_pass over narr contiguous padded arrays of (d-dimensional) points.
 // Each thread takes two lines per iteration (q and q + blockDim) and issues
 // the loads of both before their FMAs, so that two LDS round trips overlap.
-template <int P, int DA, int AX>
+template <int P, int DA, int AX, int RP = Pad<P>::PP>
 __device__ __forceinline__ int pad_line_offset(int q)
 {
-    constexpr int PP = Pad<P>::PP;
+    constexpr int PP = RP;
     constexpr int NAP = PP * ipow(P, DA - 1);
     if (AX == 0) return q * PP;
     if (AX == 1) return (q / P) * (PP * P) + (q % P);
@@ -144,10 +153,10 @@ __device__ __forceinline__ int pad_line_offset(int q)
     return a * NAP + (t % P) + PP * (t / P);
 }
 
-template <int P, int DA, int AX, typename T, int MAT, bool ACC, int NTC = 0>
+template <int P, int DA, int AX, typename T, int MAT, bool ACC, int NTC = 0, int RP = Pad<P>::PP>
 __device__ __forceinline__ void line_pass_pad(const T *__restrict__ in, T *__restrict__ out, int narr)
 {
-    constexpr int PP = Pad<P>::PP;
+    constexpr int PP = RP;
     constexpr int NL = ipow(P, DA - 1);                  // lines per array
     constexpr int S = (AX == 0) ? 1 : (AX == 1 ? PP : PP * P);
     const int nitems = narr * NL;
@@ -158,8 +167,8 @@ __device__ __forceinline__ void line_pass_pad(const T *__restrict__ in, T *__res
         const int q = b0 + threadIdx.x;
         if (b0 + nt < nitems) {
             const bool two = q + nt < nitems;
-            const int o0 = pad_line_offset<P, DA, AX>(q);
-            const int o1 = two ? pad_line_offset<P, DA, AX>(q + nt) : o0;
+            const int o0 = pad_line_offset<P, DA, AX, RP>(q);
+            const int o1 = two ? pad_line_offset<P, DA, AX, RP>(q + nt) : o0;
             T x0[P], x1[P], y0[P], y1[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) {
@@ -192,7 +201,7 @@ __device__ __forceinline__ void line_pass_pad(const T *__restrict__ in, T *__res
                 for (int i = 0; i < P; ++i) out[o1 + i * S] = y1[i];
             }
         } else if (q < nitems) {
-            const int o0 = pad_line_offset<P, DA, AX>(q);
+            const int o0 = pad_line_offset<P, DA, AX, RP>(q);
             T x0[P], y0[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) x0[k] = in[o0 + k * S];
@@ -422,7 +431,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     constexpr int FNP = F * NP;
     constexpr int NA = GRAD ? 4 : 2;
     constexpr int S = ipow(P, AX);
-    constexpr int PP = Pad<P>::PP;
+    constexpr int PP = FacePad<P>::PP;
     constexpr int NAP = PP * NP / P;                      // padded cell array
     constexpr int NAF = (D == 3) ? PP * P : PP;           // padded face array
     constexpr int SP = (AX == 0) ? 1 : (AX == 1 ? PP : PP * P);   // padded stride along AX
@@ -497,7 +506,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                     const int f = e / NP, j = e - f * NP;
                     double x = v[u].x[h];
                     if (mir[sl] && ((j / S) % P) & 1) x = -x;
-                    W[(sl * F + f) * NAP + ppos<P>(j)] = (T)x;
+                    W[(sl * F + f) * NAP + ppos<P, PP>(j)] = (T)x;
                 }
             }
         }
@@ -512,7 +521,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
             const int t = q - cf * K;
             const int c = cf / F, f = cf - c * F;
             const int lo = t % S, hi = t / S;
-            const int offL = (c * F + f) * NAP + ppos<P>(lo + hi * S * P);
+            const int offL = (c * F + f) * NAP + ppos<P, PP>(lo + hi * S * P);
             const int offR = offL + F * NAP;
             T xl[P], xr[P];
 #pragma unroll
@@ -526,7 +535,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                 tl = fma(tb.ep[m], xl[m], tl);
                 tr = fma(tb.em[m], xr[m], tr);
             }
-            const int qa = cf * NAF + ppos<P>(t);
+            const int qa = cf * NAF + ppos<P, PP>(t);
             A[0 * Q + qa] = tl;
             A[1 * Q + qa] = tr;
             if (GRAD) {
@@ -548,8 +557,8 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     // transverse transforms to the face Gauss points
     const T *tLp, *tRp, *utp = nullptr, *rnp = nullptr, *d1p = nullptr, *d2p = nullptr;
     if (D == 2) {
-        line_pass_pad<P, 1, 0, T, M_B, false, NTC>(A, Sx, NA * C * F);
-        if (GRAD) line_pass_pad<P, 1, 0, T, M_BD, false, NTC>(A + 2 * Q, Sx + 4 * Q, C * F);
+        line_pass_pad<P, 1, 0, T, M_B, false, NTC, PP>(A, Sx, NA * C * F);
+        if (GRAD) line_pass_pad<P, 1, 0, T, M_BD, false, NTC, PP>(A + 2 * Q, Sx + 4 * Q, C * F);
         __syncthreads();
         tLp = Sx;
         tRp = Sx + Q;
@@ -558,14 +567,14 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         d1p = Sx + 4 * Q;
     } else {
         // (t1, t2) = transverse axes of the face in ascending order
-        line_pass_pad<P, 2, 0, T, M_B, false, NTC>(A, Sx, NA * C * F);
-        if (GRAD) line_pass_pad<P, 2, 0, T, M_BD, false, NTC>(A + 2 * Q, Sx + 4 * Q, C * F);
+        line_pass_pad<P, 2, 0, T, M_B, false, NTC, PP>(A, Sx, NA * C * F);
+        if (GRAD) line_pass_pad<P, 2, 0, T, M_BD, false, NTC, PP>(A + 2 * Q, Sx + 4 * Q, C * F);
         __syncthreads();
-        line_pass_pad<P, 2, 1, T, M_B, false, NTC>(Sx, A, NA * C * F);
+        line_pass_pad<P, 2, 1, T, M_B, false, NTC, PP>(Sx, A, NA * C * F);
         __syncthreads();
         if (GRAD) {
-            line_pass_pad<P, 2, 1, T, M_BD, false, NTC>(Sx + 2 * Q, Sx, C * F);
-            line_pass_pad<P, 2, 1, T, M_B, false, NTC>(Sx + 4 * Q, Sx + Q, C * F);
+            line_pass_pad<P, 2, 1, T, M_BD, false, NTC, PP>(Sx + 2 * Q, Sx, C * F);
+            line_pass_pad<P, 2, 1, T, M_B, false, NTC, PP>(Sx + 4 * Q, Sx + Q, C * F);
             __syncthreads();
         }
         tLp = A;
@@ -583,7 +592,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     for (int q = tid; q < C * K; q += nt) {
         const int c = q / K, k = q - c * K;
         if (c >= nface) continue;
-        const int kp = ppos<P>(k);
+        const int kp = ppos<P, PP>(k);
         T uL[D + 2], uR[D + 2], Fh[D + 2];
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) {
@@ -735,7 +744,7 @@ size_t face_lds_bytes(int C)
     constexpr int NP = ipow(P, D);
     constexpr int K = NP / P;
     constexpr int F = Fld<D, PH>::F;
-    constexpr int PP = Pad<P>::PP;
+    constexpr int PP = FacePad<P>::PP;
     const size_t hdr = (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16;
     const size_t Q = (size_t)C * F * (PP * K / P);
     const size_t W = (size_t)(C + 1) * F * (PP * NP / P);
