@@ -149,6 +149,24 @@ def test_max_dt_and_totals(dim, order):
     np.testing.assert_allclose(gpu.totals(w), ref.totals(w0), rtol=1e-14, atol=1e-15)
 
 
+def test_max_dt_many_partial_blocks_and_nan():
+    """The CFL reduction over > 4 x 1024 per-block partials: the exact maxima
+    (placed in the last cell, i.e. the last partial) and NaN propagation."""
+    dim, n, order = 2, (320, 256), 4
+    say("dt many blocks")
+    gpu, ref = pair(dim, n, order, cfl=0.5, **PHYS["euler"])
+    w0 = state(dim, n, order, ref, seed=57)
+    w0[-1, dim + 1, 0] *= 3.0                 # hotter last cell: c_max lives in the last partial
+    w = torch.tensor(w0, device="cuda")
+    dt, cm, vm = gpu.max_dt(w)
+    dtr, cmr, vmr = ref.max_dt(w0)
+    assert abs(cm - cmr) <= 1e-14 * cmr and abs(vm - vmr) <= 1e-14 * vmr and abs(dt - dtr) <= 1e-14 * dtr
+    wn = w0.copy()
+    wn[n[0] * n[1] // 2, 0, 3] = float("nan")
+    dtn, cmn, _ = gpu.max_dt(torch.tensor(wn, device="cuda"))
+    assert np.isnan(dtn) and np.isnan(cmn)
+
+
 def test_step_cfl_uses_device_dt():
     dim, n, order = 2, (13, 9), 3
     say("step_cfl")
