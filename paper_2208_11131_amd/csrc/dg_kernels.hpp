@@ -262,6 +262,39 @@ __device__ __forceinline__ DV<VW> zdv()
     return r;
 }
 
+// D^T pass along AX accumulated into out, fused with the surface lift of the
+// same lines: out_i += sum_k D(k, i) in_k + L_i(-1) Fl - L_i(+1) Fu, where
+// (Fl, Fu) = lf[r] are the lower / upper face fluxes of line r of this thread
+// (line q = threadIdx.x + r NTC; the block size NTC is fixed).
+template <int P, int DA, int AX, typename T, int NTC, int NR>
+__device__ __forceinline__ void dt_lift_pass(const T *__restrict__ in, T *__restrict__ out, int nitems,
+                                             const T (*lf)[2])
+{
+    constexpr int PP = Pad<P>::PP;
+    constexpr int S = (AX == 0) ? 1 : (AX == 1 ? PP : PP * P);
+    const Tab<T> &tb = TabSel<T>::get(P);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int q = threadIdx.x + r * NTC;
+        if (q < nitems) {
+            const int o = pad_line_offset<P, DA, AX>(q);
+            T x[P], y[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                x[k] = in[o + k * S];
+                y[k] = out[o + k * S];
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                T acc = y[i];
+#pragma unroll
+                for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_DT>(k, i), x[k], acc);
+                out[o + i * S] = acc + (tb.Lm[i] * lf[r][0] - tb.Lp[i] * lf[r][1]);
+            }
+        }
+    }
+}
+
 // Fields per physics variant: PH = 0 Euler, 1 Navier-Stokes, 2 artificial
 // viscosity (alpha field; Navier-Stokes terms switched at run time).
 template <int D, int PH>
@@ -989,10 +1022,15 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
 
     // Global reads of the later phases are issued early, after the flux
     // phase (the register peak), so their latency overlaps the D^T, lift and
-    // projection passes: the face fluxes of the first NLF lift rounds and the
-    // RK inputs of the first NLD elements of each thread (the rest, if any,
-    // are read where they are used).  With a fixed tile both counts are exact.
-    constexpr int NLF = (CC > 0 && NTC > 0) ? (CC * Fc * K + NTC - 1) / NTC : 1;
+    // projection passes: the face fluxes of the lift and the RK inputs of the
+    // first NLD groups of each thread (the rest, if any, are read where they
+    // are used).  With a fixed tile the counts are exact, and the lift is
+    // fused into the D^T passes: line q of the D^T pass along a is the line
+    // (field f, cell c, transverse point t) whose end points the two a-faces
+    // of cell c at face point t lift.
+    constexpr bool FUSED = CC > 0 && NTC > 0;
+    constexpr int NLF = 1;                                         // lift rounds read early (generic tile)
+    constexpr int NDT = FUSED ? (CC * Fc * K + NTC - 1) / NTC : 1;   // D^T lines per thread
     constexpr int NLD0 = (CC > 0 && NTC > 0) ? (CC * FNP / VW + NTC - 1) / NTC : 2;
     constexpr int NLD = NLD0 < 8 ? NLD0 : 8;
     const int nlift = C * Fc * K;
@@ -1009,17 +1047,26 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         }
     };
     T lfl[NLF][D], lfu[NLF][D];
+    T dlf[D][NDT][2];
+    if constexpr (FUSED) {
 #pragma unroll
-    for (int rr = 0; rr < NLF; ++rr) lift_load(tid + rr * nt, lfl[rr], lfu[rr]);
-
-    // 5. Q += sum_a D_a^T (w f_a)
-    line_pass_pad<P, D, 0, T, M_DT, true, NTC>(G, U, Fc * C);
-    __syncthreads();
-    line_pass_pad<P, D, 1, T, M_DT, true, NTC>(G + F * CNP, U, Fc * C);
-    __syncthreads();
-    if (D == 3) {
-        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_DT, true, NTC>(G + 2 * F * CNP, U, Fc * C);
-        __syncthreads();
+        for (int r = 0; r < NDT; ++r) {
+            const int q = tid + r * nt;
+            const bool act = q < nlift;
+            const int arr = act ? q / K : 0;            // array (f, c) of the U layout: f C + c
+            const int f = arr / C, c = arr - f * C;
+            const int t = q - arr * K;                  // transverse point = face point
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                const T *fb = (const T *)a.fb + geo.fb_off[ax];
+                const long long flo = fidx[(c * D + ax) * 2], fhi = fidx[(c * D + ax) * 2 + 1];
+                dlf[ax][r][0] = act ? fb[flo * (Fc * K) + f * K + t] : T(0);
+                dlf[ax][r][1] = act ? fb[fhi * (Fc * K) + f * K + t] : T(0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int rr = 0; rr < NLF; ++rr) lift_load(tid + rr * nt, lfl[rr], lfu[rr]);
     }
 
     const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
@@ -1034,36 +1081,52 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         px[m] = (ok && a.x2) ? ldv<VW>(a.x2 + gi) : zdv<VW>();
     }
 
-    // 6. surface lift in point space: Q(i, k) += L_i(-1) F_lower(k) - L_i(+1) F_upper(k),
-    //    applied axis by axis (a barrier between axes: their lines intersect).
-    {
-        auto lift = [&](int q, const T *Fl, const T *Fu) {
+    // 5.-6. Q += sum_a [D_a^T (w f_a) + surface lift of the two a-faces], axis by axis
+    if constexpr (FUSED) {
+        dt_lift_pass<P, D, 0, T, NTC, NDT>(G, U, Fc * C * K, dlf[0]);
+        __syncthreads();
+        dt_lift_pass<P, D, 1, T, NTC, NDT>(G + F * CNP, U, Fc * C * K, dlf[1]);
+        __syncthreads();
+        if (D == 3) {
+            dt_lift_pass<P, D, (D == 3 ? 2 : 0), T, NTC, NDT>(G + 2 * F * CNP, U, Fc * C * K, dlf[D - 1]);
+            __syncthreads();
+        }
+    } else {
+        // per axis: the D^T pass, then the lift of that axis, Q(i, k) +=
+        // L_i(-1) F_lower(k) - L_i(+1) F_upper(k) (same summation order as
+        // the fused passes, so both give the same bits)
+        const int rounds = (nlift + nt - 1) / nt;          // uniform over the block
+        auto lift_ax = [&](int ax, int q, T Fl, T Fu) {
             const bool act = q < nlift;
             const int c = act ? q / (Fc * K) : 0;
             const int r = q - c * (Fc * K);
             const int f = act ? r / K : 0, k = act ? r - f * K : 0;
+            const int S = (ax == 0) ? 1 : (ax == 1 ? P : P * P);
+            if (act) {
+                const int lo = k % S, hi = k / S;
+                T *po = U + f * CNP + c * NAP;
+                const int j0 = lo + hi * S * P;
 #pragma unroll
-            for (int ax = 0; ax < D; ++ax) {
-                const int S = (ax == 0) ? 1 : (ax == 1 ? P : P * P);
-                if (act) {
-                    const int lo = k % S, hi = k / S;
-                    T *po = U + f * CNP + c * NAP;
-                    const int j0 = lo + hi * S * P;
-#pragma unroll
-                    for (int i = 0; i < P; ++i) po[ppos<P>(j0 + i * S)] += tb.Lm[i] * Fl[ax] - tb.Lp[i] * Fu[ax];
-                }
-                __syncthreads();
+                for (int i = 0; i < P; ++i) po[ppos<P>(j0 + i * S)] += tb.Lm[i] * Fl - tb.Lp[i] * Fu;
             }
         };
-        const int rounds = (nlift + nt - 1) / nt;          // uniform over the block
+        auto axis = [&](auto axc) {
+            constexpr int AX = decltype(axc)::value;
+            line_pass_pad<P, D, AX, T, M_DT, true, NTC>(G + AX * F * CNP, U, Fc * C);
+            __syncthreads();
 #pragma unroll
-        for (int rr = 0; rr < NLF; ++rr)
-            if (rr < rounds) lift(tid + rr * nt, lfl[rr], lfu[rr]);
-        for (int rr = NLF; rr < rounds; ++rr) {
-            T Fl[D], Fu[D];
-            lift_load(tid + rr * nt, Fl, Fu);
-            lift(tid + rr * nt, Fl, Fu);
-        }
+            for (int rr = 0; rr < NLF; ++rr)
+                if (rr < rounds) lift_ax(AX, tid + rr * nt, lfl[rr][AX], lfu[rr][AX]);
+            for (int rr = NLF; rr < rounds; ++rr) {
+                T Fl[D], Fu[D];
+                lift_load(tid + rr * nt, Fl, Fu);
+                lift_ax(AX, tid + rr * nt, Fl[AX], Fu[AX]);
+            }
+            __syncthreads();
+        };
+        axis(std::integral_constant<int, 0>{});
+        axis(std::integral_constant<int, 1>{});
+        if constexpr (D == 3) axis(std::integral_constant<int, 2>{});
     }
 
     // 7. point -> modal projection of every stored field
