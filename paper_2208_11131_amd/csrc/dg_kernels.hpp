@@ -826,56 +826,11 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     T *X1 = (D == 3) ? Ub : G;
     const Tab<T> &tb = TabSel<T>::get(P);
 
-    // 1. load the tile's weights (and forcing coefficients); per-cell data.
-    //    UNR loads per thread are issued before their LDS stores.
+    // 1. per-cell data (the weights themselves are read by the first pass)
     constexpr int UNR = 4;
     constexpr int VW = (FNP % 2 == 0) ? 2 : 1;   // doubles per global access
     const long long gbase = c0 * FNP, gend = NC * FNP;
     const int ngrp = C * FNP / VW;
-    for (int i0 = tid; i0 < ngrp; i0 += UNR * nt) {
-        DV<VW> v[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int e = (i0 + u * nt) * VW;
-            long long gi = gbase + e;
-            if (gi >= gend) gi = (NC - 1) * FNP + e % FNP;   // tail cells: copies of the last cell
-            v[u] = (i0 + u * nt < ngrp) ? ldv<VW>(a.cur + gi) : zdv<VW>();
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            if (i0 + u * nt < ngrp) {
-#pragma unroll
-                for (int h = 0; h < VW; ++h) {
-                    const int i = (i0 + u * nt) * VW + h;
-                    const int c = i / FNP, r = i - c * FNP;
-                    const int f = r / NP, j = r - f * NP;
-                    X0[f * CNP + c * NAP + ppos<P>(j)] = (T)v[u].x[h];
-                }
-            }
-        }
-    }
-    if (forced) {
-        for (int i0 = tid; i0 < C * D * NP; i0 += UNR * nt) {
-            double v[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int i = i0 + u * nt;
-                const int c = i / (D * NP), r = i - c * (D * NP);
-                long long cc = c0 + c;
-                if (cc >= NC) cc = NC - 1;
-                v[u] = (i < C * D * NP) ? a.forcing[cc * D * NP + r] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int i = i0 + u * nt;
-                if (i < C * D * NP) {
-                    const int c = i / (D * NP), r = i - c * (D * NP);
-                    const int f = r / NP, j = r - f * NP;
-                    X0[(F + f) * CNP + c * NAP + ppos<P>(j)] = (T)v[u];
-                }
-            }
-        }
-    }
     if (tid == 0) *blkflag = 0;
     for (int cl = tid; cl < C; cl += nt) {
         long long cc = c0 + cl;
@@ -926,8 +881,42 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     }
     __syncthreads();
 
-    // 2. point values of all fields: one operator pass per axis
-    line_pass_pad<P, D, 0, T, M_B, false, NTC>(X0, X1, Fx * C);
+    // 2. point values of all fields: one operator pass per axis.  The pass
+    //    along x reads each line's p modal weights (contiguous in HBM)
+    //    straight from the state or forcing arrays, so the weights never
+    //    pass through LDS; the same FMA chain as the LDS passes.
+    {
+        constexpr int VWL = (P % 2 == 0) ? 2 : 1;       // state weights per load
+        const int nitems = Fx * C * K;                  // K = p^(d-1) lines per array
+        for (int q = tid; q < nitems; q += nt) {
+            const int arr = q / K, t = q - arr * K;
+            const int f = arr / C, c = arr - f * C;
+            long long cc = c0 + c;
+            if (cc >= NC) cc = NC - 1;                  // tail cells: copies of the last cell
+            T x[P];
+            if (f < F) {
+                const double *src = a.cur + cc * FNP + f * NP + t * P;
+#pragma unroll
+                for (int k = 0; k < P; k += VWL) {
+                    const DV<VWL> v = ldv<VWL>(src + k);
+#pragma unroll
+                    for (int h = 0; h < VWL; ++h) x[k + h] = (T)v.x[h];
+                }
+            } else {
+                const double *src = a.forcing + cc * (D * NP) + (f - F) * NP + t * P;
+#pragma unroll
+                for (int k = 0; k < P; ++k) x[k] = (T)src[k];
+            }
+            const int o = pad_line_offset<P, D, 0>(q);
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                T acc = T(0);
+#pragma unroll
+                for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_B>(k, i), x[k], acc);
+                X1[o + i] = acc;
+            }
+        }
+    }
     __syncthreads();
     line_pass_pad<P, D, 1, T, M_B, false, NTC>(X1, X0, Fx * C);
     __syncthreads();
