@@ -790,6 +790,15 @@ size_t face_lds_bytes(int C)
 // volume kernel
 // ---------------------------------------------------------------------------
 
+// LDS header of the volume kernel: face indices [C][D][2] (long long), wiggle
+// source [C] and new cell means [C][D+2] (double), the block's error flag;
+// rounded to 16 bytes.
+template <int D>
+__host__ __device__ constexpr size_t vol_hdr_bytes(int C)
+{
+    return ((C * (2 * D * sizeof(long long) + (1 + D + 2) * sizeof(double)) + sizeof(int) + 15) / 16) * 16;
+}
+
 // CC, NTC, FO: cells per block, threads per block and forcing (0 off, 1 on)
 // fixed at compile time (0 / 0 / -1 = taken from the launch).  Fixing them
 // removes the runtime tile arithmetic; the results are the same bits.
@@ -819,18 +828,15 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     // free outside the gradient / flux phases.
     long long *fidx = (long long *)smem;      // [C][D][2] lower/upper face index per axis
     double *cellv = (double *)(fidx + 2 * D * C);   // [C]: wiggle source
-    int *blkflag = (int *)(cellv + C);
-    T *Ub = (T *)(smem + ((C * (2 * D * sizeof(long long) + sizeof(double)) + sizeof(int) + 15) / 16) * 16);
+    double *cmean = cellv + C;                // [C][D+2]: new cell means (checks)
+    int *blkflag = (int *)(cmean + C * (D + 2));
+    T *Ub = (T *)(smem + vol_hdr_bytes<D>(C));
     T *G = Ub + Fx * CNP;
     T *X0 = (D == 3) ? G : Ub;     // the last of the D passes lands in Ub
     T *X1 = (D == 3) ? Ub : G;
     const Tab<T> &tb = TabSel<T>::get(P);
 
     // 1. per-cell data (the weights themselves are read by the first pass)
-    constexpr int UNR = 4;
-    constexpr int VW = (FNP % 2 == 0) ? 2 : 1;   // doubles per global access
-    const long long gbase = c0 * FNP, gend = NC * FNP;
-    const int ngrp = C * FNP / VW;
     if (tid == 0) *blkflag = 0;
     for (int cl = tid; cl < C; cl += nt) {
         long long cc = c0 + cl;
@@ -1020,8 +1026,10 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     constexpr bool FUSED = CC > 0 && NTC > 0;
     constexpr int NLF = 1;                                         // lift rounds read early (generic tile)
     constexpr int NDT = FUSED ? (CC * Fc * K + NTC - 1) / NTC : 1;   // D^T lines per thread
-    constexpr int NLD0 = (CC > 0 && NTC > 0) ? (CC * FNP / VW + NTC - 1) / NTC : 2;
-    constexpr int NLD = NLD0 < 8 ? NLD0 : 8;
+    // lines of the final (x) projection pass per thread, and how many of them
+    // get their RK inputs read early (p doubles per array per line)
+    constexpr int NBL0 = FUSED ? (CC * F * K + NTC - 1) / NTC : 0;
+    constexpr int NBL = (NBL0 * P <= 8) ? NBL0 : 0;
     const int nlift = C * Fc * K;
     auto lift_load = [&](int q, T *Fl, T *Fu) {
         const bool act = q < nlift;
@@ -1059,16 +1067,32 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     }
 
     const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
-    DV<VW> pc[NLD], pb[NLD], px[NLD];
+    constexpr int VWL = (P % 2 == 0) ? 2 : 1;      // weights per access along a line
+    const int nx = F * C * K;                      // lines of the final projection pass
+    // RK inputs of a final-pass line: p consecutive weights of cur / base / x2
+    auto rk_load = [&](int q, double *cu, double *ba, double *x2) {
+        const int arr = q / K, t = q - arr * K;
+        const int f = arr / C, c = arr - f * C;
+        const long long cc = c0 + c;
+        const bool ok = q < nx && cc < NC;
+        const long long gi = cc * FNP + f * NP + t * P;
 #pragma unroll
-    for (int m = 0; m < NLD; ++m) {
-        const int g = tid + m * nt;
-        const long long gi = gbase + (long long)g * VW;
-        const bool ok = g < ngrp && gi < gend;
-        pc[m] = ok ? ldv<VW>(a.cur + gi) : zdv<VW>();
-        pb[m] = (ok && a.base) ? ldv<VW>(a.base + gi) : zdv<VW>();
-        px[m] = (ok && a.x2) ? ldv<VW>(a.x2 + gi) : zdv<VW>();
-    }
+        for (int k = 0; k < P; k += VWL) {
+            const DV<VWL> zc = zdv<VWL>();
+            const DV<VWL> vc = ok ? ldv<VWL>(a.cur + gi + k) : zc;
+            const DV<VWL> vb = (ok && a.base) ? ldv<VWL>(a.base + gi + k) : zc;
+            const DV<VWL> vx = (ok && a.x2) ? ldv<VWL>(a.x2 + gi + k) : zc;
+#pragma unroll
+            for (int h = 0; h < VWL; ++h) {
+                cu[k + h] = vc.x[h];
+                ba[k + h] = vb.x[h];
+                x2[k + h] = vx.x[h];
+            }
+        }
+    };
+    double pcu[NBL > 0 ? NBL : 1][P], pba[NBL > 0 ? NBL : 1][P], px2[NBL > 0 ? NBL : 1][P];
+#pragma unroll
+    for (int r = 0; r < NBL; ++r) rk_load(tid + r * nt, pcu[r], pba[r], px2[r]);
 
     // 5.-6. Q += sum_a [D_a^T (w f_a) + surface lift of the two a-faces], axis by axis
     if constexpr (FUSED) {
@@ -1118,58 +1142,69 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         if constexpr (D == 3) axis(std::integral_constant<int, 2>{});
     }
 
-    // 7. point -> modal projection of every stored field
-    line_pass_pad<P, D, 0, T, M_BT, false, NTC>(U, Wk, F * C);
-    __syncthreads();
-    line_pass_pad<P, D, 1, T, M_BT, false, NTC>(Wk, U, F * C);
-    __syncthreads();
+    // 7.-8. point -> modal projection, last axis first; the pass along x
+    //       (each line = p consecutive modal weights) is fused with the FP64
+    //       RK combination and the write-back, p weights per thread.
     if (D == 3) {
         line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_BT, false, NTC>(U, Wk, F * C);
         __syncthreads();
+        line_pass_pad<P, D, 1, T, M_BT, false, NTC>(Wk, U, F * C);
+        __syncthreads();
+    } else {
+        line_pass_pad<P, D, 1, T, M_BT, false, NTC>(U, Wk, F * C);
+        __syncthreads();
     }
-    const T *V = (D == 3) ? Wk : U;
-
-    // 8. RK combination in FP64 and write-back, VW consecutive weights per access
+    const T *Xs = (D == 3) ? U : Wk;   // input of the x pass
+    T *Vl = (D == 3) ? Wk : U;         // the modal RHS, kept in LDS for the AV sensor rate
     const double pref = ph.pref;
     int bad = 0;
-    auto combine = [&](int g, long long gi, const DV<VW> &cu, const DV<VW> &ba, const DV<VW> &x2) {
-        DV<VW> o, o2;
+    auto xpass_rk = [&](int q, const double *cu, const double *ba, const double *x2) {
+        const int arr = q / K, t = q - arr * K;
+        const int f = arr / C, c = arr - f * C;
+        const long long cc = c0 + c;
+        const int o = pad_line_offset<P, D, 0>(q);
+        T x[P], y[P];
 #pragma unroll
-        for (int h = 0; h < VW; ++h) {
-            const int i = g * VW + h;
-            const int c = i / FNP, r = i - c * FNP;
-            const int f = r / NP, j = r - f * NP;
-            const double L = pref * (double)V[f * CNP + c * NAP + ppos<P>(j)];
-            o.x[h] = a.c_cur * cu.x[h] + a.c_L * dt * L;
-            if (a.base) o.x[h] += a.c_base * ba.x[h];
-            o2.x[h] = a.d_cur * cu.x[h] + a.d_L * dt * L + (a.x2 ? a.d_x2 * x2.x[h] : 0.0);
-            if (!isfinite(o.x[h])) bad |= 2;
+        for (int k = 0; k < P; ++k) x[k] = Xs[o + k];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_BT>(k, i), x[k], acc);
+            y[i] = acc;
+            if (PH == 2) Vl[o + i] = acc;
         }
-        if (a.out2) stv<VW>(a.out2 + gi, o2);
-        stv<VW>(a.out + gi, o);
+        if (cc >= NC) return;
+        const long long gi = cc * FNP + f * NP + t * P;
+        double ov[P], o2v[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const double L = pref * (double)y[i];
+            ov[i] = a.c_cur * cu[i] + a.c_L * dt * L;
+            if (a.base) ov[i] += a.c_base * ba[i];
+            o2v[i] = a.d_cur * cu[i] + a.d_L * dt * L + (a.x2 ? a.d_x2 * x2[i] : 0.0);
+            if (!isfinite(ov[i])) bad |= 2;
+        }
+#pragma unroll
+        for (int k = 0; k < P; k += VWL) {
+            DV<VWL> vo, vo2;
+#pragma unroll
+            for (int h = 0; h < VWL; ++h) {
+                vo.x[h] = ov[k + h];
+                vo2.x[h] = o2v[k + h];
+            }
+            if (a.out2) stv<VWL>(a.out2 + gi + k, vo2);
+            stv<VWL>(a.out + gi + k, vo);
+        }
+        if (t == 0 && f < D + 2) cmean[c * (D + 2) + f] = ov[0];
     };
 #pragma unroll
-    for (int m = 0; m < NLD; ++m) {
-        const int g = tid + m * nt;
-        const long long gi = gbase + (long long)g * VW;
-        if (g < ngrp && gi < gend) combine(g, gi, pc[m], pb[m], px[m]);
-    }
-    for (int i0 = tid + NLD * nt; i0 < ngrp; i0 += UNR * nt) {
-        DV<VW> cu[UNR], ba[UNR], x2[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const long long gi = gbase + (long long)(i0 + u * nt) * VW;
-            const bool ok = (i0 + u * nt < ngrp) && gi < gend;
-            cu[u] = ok ? ldv<VW>(a.cur + gi) : zdv<VW>();
-            ba[u] = (ok && a.base) ? ldv<VW>(a.base + gi) : zdv<VW>();
-            x2[u] = (ok && a.x2) ? ldv<VW>(a.x2 + gi) : zdv<VW>();
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int g = i0 + u * nt;
-            const long long gi = gbase + (long long)g * VW;
-            if (g < ngrp && gi < gend) combine(g, gi, cu[u], ba[u], x2[u]);
-        }
+    for (int r = 0; r < NBL; ++r)
+        if (tid + r * nt < nx) xpass_rk(tid + r * nt, pcu[r], pba[r], px2[r]);
+    for (int q = tid + NBL * nt; q < nx; q += nt) {
+        double cu[P], ba[P], x2[P];
+        rk_load(q, cu, ba, x2);
+        xpass_rk(q, cu, ba, x2);
     }
     if (bad) atomicOr(blkflag, bad);
     __syncthreads();
@@ -1178,18 +1213,18 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     for (int cl = tid; cl < C; cl += nt) {
         const long long cc = c0 + cl;
         if (cc >= NC) continue;
-        const double *o = a.out + cc * FNP;
+        const double *o = cmean + cl * (D + 2);
         const double rho = o[0];
         double m2 = 0.0;
-        for (int i = 0; i < D; ++i) m2 += o[(1 + i) * NP] * o[(1 + i) * NP];
-        const double pm = (ph.gamma - 1.0) * (o[(D + 1) * NP] - 0.5 * m2 / rho);
+        for (int i = 0; i < D; ++i) m2 += o[1 + i] * o[1 + i];
+        const double pm = (ph.gamma - 1.0) * (o[D + 1] - 0.5 * m2 / rho);
         if (a.check && !(rho > 0.0 && pm > 0.0)) atomicOr(blkflag, 1);
         if (PH == 2 && a.R_out) {
             const double *wr = a.cur + cc * FNP;
             double Aa = 0.0, Tt = 0.0, ad = 0.0, td = 0.0;
             for (int m = 0; m < NP; ++m) {
                 const double x = wr[m];
-                const double xd = pref * (double)V[cl * NAP + ppos<P>(m)];
+                const double xd = pref * (double)Vl[cl * NAP + ppos<P>(m)];
                 Aa += x * x;
                 ad += x * xd;
                 bool tp = false;
@@ -1292,8 +1327,7 @@ size_t vol_lds_bytes(int C, int Fx)
 {
     constexpr int NP = Pad<P>::PP * ipow(P, D - 1);   // padded per-cell array
     constexpr int F = Fld<D, PH>::F;
-    const size_t hdr = ((C * (2 * D * sizeof(long long) + sizeof(double)) + sizeof(int) + 15) / 16) * 16;
-    return hdr + sizeof(T) * ((size_t)C * Fx * NP + (size_t)C * D * F * NP);
+    return vol_hdr_bytes<D>(C) + sizeof(T) * ((size_t)C * Fx * NP + (size_t)C * D * F * NP);
 }
 
 // ---------------------------------------------------------------------------
