@@ -15,6 +15,9 @@ Extra objects on the JSON line:
   roofline     dominant kernel (by device time): algorithmic bytes or flops per
                launch over its average duration, measured with HIP events on
                the launch stream around every kernel of the timed region;
+  stage_roofline  the whole stage (all kernels and launch gaps): the stage's
+               algorithmic bytes and both kernels' flops over the measured
+               time per stage, against the HBM and the ALU peaks;
   cpu_baseline the CPU oracle (plain FP64, OpenMP) timed on one full RK step
                of the same workload;
   fp32_bulk    the same workload with FP32 bulk arithmetic (FP64 state/RK);
@@ -208,7 +211,15 @@ def measure(name, order, precision, steps, warmup, device="cuda"):
                        "algorithmic_bytes": by, "algorithmic_flops": fl}
         kern[k]["frac"] = kern[k]["achieved"] / kern[k]["peak"]
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    res = {"value": value, "ms": ms, "wall_s": wall, "stages": stages, "dofs": dofs, "desc": desc, "steps": steps + warmup,
+    # the whole stage (every kernel and launch gap) against the same counts:
+    # algorithmic bytes of the stage (charged to the volume kernel above) and
+    # the flops of both kernels, over the measured time per stage
+    st_s = ms * 1e-3 / (steps * stages)
+    stage = {"us": st_s * 1e6, "algorithmic_bytes": vol_bytes, "algorithmic_flops": vol_fl + face_fl,
+             "achieved_gbs": vol_bytes / st_s / 1e9, "frac_hbm": vol_bytes / st_s / 1e9 / HBM_PEAK_GBS,
+             "achieved_tflops": (vol_fl + face_fl) / st_s / 1e12,
+             "frac_alu": (vol_fl + face_fl) / st_s / 1e12 / peak_tf}
+    res = {"value": value, "stage": stage, "ms": ms, "wall_s": wall, "stages": stages, "dofs": dofs, "desc": desc, "steps": steps + warmup,
            "kernels": kern, "dominant": dom, "cfl_ms": kt["cfl"][0], "solver": s, "state": w,
            "forcing": f}
     return res
@@ -336,6 +347,7 @@ def main():
         "config": dict(res["desc"], stages_per_step=res["stages"], dofs=res["dofs"],
                        step="device CFL reduction + full SSP-RK step"),
         "roofline": roof,
+        "stage_roofline": res["stage"],
     }
     desc, stages, dofs = res["desc"], res["stages"], res["dofs"]
     w64 = res["state"].cpu().numpy()
@@ -361,7 +373,12 @@ def main():
         line["turbulence_3d"] = {"value": r3["value"], "ms_per_step": r3["ms"] / 5, "config": r3["desc"],
                                  "roofline": {"kernel": r3["dominant"], "bound": d3["bound"],
                                               "achieved": d3["achieved"], "peak": d3["peak"], "unit": d3["unit"],
-                                              "frac": d3["frac"], "avg_us": d3["avg_us"]}}
+                                              "frac": d3["frac"], "avg_us": d3["avg_us"],
+                                              "other_kernels": {k: {kk: v[kk] for kk in
+                                                                    ("bound", "achieved", "unit", "frac", "avg_us")}
+                                                                for k, v in r3["kernels"].items()
+                                                                if k != r3["dominant"]}},
+                                 "stage_roofline": r3["stage"]}
         del r3
         torch.cuda.empty_cache()
         print("bench: ensemble", file=sys.stderr, flush=True)

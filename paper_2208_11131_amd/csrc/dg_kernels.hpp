@@ -492,11 +492,12 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
 
     long long *cellidx = (long long *)smem;               // [C+1]
     int *mir = (int *)(cellidx + (C + 1));                // [C+1]
-    // LDS: cell coefficients W, overlaid after the contraction by the scratch
-    // Sx (5 Q entries), then the contraction results A (NA Q entries)
-    T *W = (T *)(smem + (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16);   // [C+1][F][NAP]
-    T *Sx = W;                                            // scratch [5][C][F][NAF]
-    T *A = W + max((C + 1) * F * NAP, 5 * Q);             // [NA][C][F][NAF]
+    // LDS: the scratch Sx of the transverse passes (5 Q entries; during the
+    // normal contraction it holds the upper cells' recovery partial sums),
+    // then the contraction results A (NA Q entries).  The cells themselves
+    // are read straight from HBM by the normal contraction.
+    T *Sx = (T *)(smem + (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16);   // [5][C][F][NAF]
+    T *A = Sx + 5 * Q;                                    // [NA][C][F][NAF]
 
     for (int s = tid; s <= C; s += nt) {
         int ca = a0 + s - 1;
@@ -518,74 +519,82 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         mir[s] = m;
     }
     __syncthreads();
-    constexpr int UNR = 4;      // loads in flight per thread
-    constexpr int VW = (FNP % 2 == 0) ? 2 : 1;   // doubles per global access
-    const int ngrp = (C + 1) * FNP / VW;
-    for (int i0 = tid; i0 < ngrp; i0 += UNR * nt) {
-        DV<VW> v[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int i = (i0 + u * nt) * VW;
-            const int sl = i0 + u * nt < ngrp ? i / FNP : 0;
-            v[u] = i0 + u * nt < ngrp ? ldv<VW>(a.w + cellidx[sl] * FNP + (i - sl * FNP)) : zdv<VW>();
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            if (i0 + u * nt < ngrp) {
-#pragma unroll
-                for (int h = 0; h < VW; ++h) {
-                    const int i = (i0 + u * nt) * VW + h;
-                    const int sl = i / FNP, e = i - sl * FNP;
-                    const int f = e / NP, j = e - f * NP;
-                    double x = v[u].x[h];
-                    if (mir[sl] && ((j / S) % P) & 1) x = -x;
-                    W[(sl * F + f) * NAP + ppos<P, PP>(j)] = (T)x;
-                }
-            }
-        }
-    }
-    __syncthreads();
-
-    // normal contraction: traces (and recovery partial sums) per transverse mode
+    // normal contraction, one item per (slot s, field f, transverse mode t):
+    // the p weights of the line along the normal are read from HBM (mirrored
+    // ghost: odd normal modes negated); slot s is the lower cell of face s
+    // (trace P~(+1) and the lower-side recovery partial sums) and the upper
+    // cell of face s - 1 (trace P~(-1) and the upper-side partial sums).  The
+    // two sides' partial sums are added after the barrier.
     {
         const Tab<T> &tb = TabSel<T>::get(P);
-        for (int q = tid; q < C * F * K; q += nt) {
-            const int cf = q / K;
-            const int t = q - cf * K;
-            const int c = cf / F, f = cf - c * F;
+        T *A2u = Sx, *A3u = Sx + Q;                       // upper-side partial sums
+        for (int q = tid; q < (C + 1) * F * K; q += nt) {
+            const int sf = q / K;
+            const int t = q - sf * K;
+            const int sl = sf / F, f = sf - sl * F;
             const int lo = t % S, hi = t / S;
-            const int offL = (c * F + f) * NAP + ppos<P, PP>(lo + hi * S * P);
-            const int offR = offL + F * NAP;
-            T xl[P], xr[P];
+            const double *src = a.w + cellidx[sl] * FNP + f * NP + lo + hi * S * P;
+            const bool mr = mir[sl] != 0;
+            T x[P];
+            if (AX == 0 && P % 2 == 0) {
 #pragma unroll
-            for (int m = 0; m < P; ++m) {
-                xl[m] = W[offL + m * SP];
-                xr[m] = W[offR + m * SP];
-            }
-            T tl = T(0), tr = T(0);
-#pragma unroll
-            for (int m = 0; m < P; ++m) {
-                tl = fma(tb.ep[m], xl[m], tl);
-                tr = fma(tb.em[m], xr[m], tr);
-            }
-            const int qa = cf * NAF + ppos<P, PP>(t);
-            A[0 * Q + qa] = tl;
-            A[1 * Q + qa] = tr;
-            if (GRAD) {
-                T rv = T(0), rn = T(0);
+                for (int m = 0; m < P; m += 2) {
+                    const DV<2> v = ldv<2>(src + m);
+                    x[m] = (T)v.x[0];
+                    x[m + 1] = (T)(mr ? -v.x[1] : v.x[1]);
+                }
+            } else {
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
-                    rv = fma(tb.rvL[m], xl[m], rv);
-                    rv = fma(tb.rvR[m], xr[m], rv);
-                    rn = fma(tb.rdL[m], xl[m], rn);
-                    rn = fma(tb.rdR[m], xr[m], rn);
+                    const double v = src[m * S];
+                    x[m] = (T)((mr && (m & 1)) ? -v : v);
                 }
-                A[2 * Q + qa] = rv;
-                A[3 * Q + qa] = rn;
+            }
+            const int pt = ppos<P, PP>(t);
+            if (sl < C) {
+                const int qa = (sl * F + f) * NAF + pt;
+                T tl = T(0);
+#pragma unroll
+                for (int m = 0; m < P; ++m) tl = fma(tb.ep[m], x[m], tl);
+                A[0 * Q + qa] = tl;
+                if (GRAD) {
+                    T rv = T(0), rn = T(0);
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        rv = fma(tb.rvL[m], x[m], rv);
+                        rn = fma(tb.rdL[m], x[m], rn);
+                    }
+                    A[2 * Q + qa] = rv;
+                    A[3 * Q + qa] = rn;
+                }
+            }
+            if (sl > 0) {
+                const int qa = ((sl - 1) * F + f) * NAF + pt;
+                T tr = T(0);
+#pragma unroll
+                for (int m = 0; m < P; ++m) tr = fma(tb.em[m], x[m], tr);
+                A[1 * Q + qa] = tr;
+                if (GRAD) {
+                    T rv = T(0), rn = T(0);
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        rv = fma(tb.rvR[m], x[m], rv);
+                        rn = fma(tb.rdR[m], x[m], rn);
+                    }
+                    A2u[qa] = rv;
+                    A3u[qa] = rn;
+                }
             }
         }
+        __syncthreads();
+        if (GRAD) {
+            for (int i = tid; i < Q; i += nt) {
+                A[2 * Q + i] += A2u[i];
+                A[3 * Q + i] += A3u[i];
+            }
+            __syncthreads();
+        }
     }
-    __syncthreads();
 
     // transverse transforms to the face Gauss points
     const T *tLp, *tRp, *utp = nullptr, *rnp = nullptr, *d1p = nullptr, *d2p = nullptr;
@@ -767,10 +776,8 @@ __global__ void __launch_bounds__(NT) face_kernel_batched_fixed(const BoxDesc *b
 }
 
 
-// LDS bytes of the face kernel for pencils of C faces: slot indices, the C+1
-// cells' coefficients W overlaid by a scratch of 5 C F p^(d-1) (W is dead
-// after the normal contraction), and the contraction results A (NA C F
-// p^(d-1)).
+// LDS bytes of the face kernel for pencils of C faces: slot indices, a
+// scratch of 5 C F p^(d-1) and the contraction results A (NA C F p^(d-1)).
 template <int D, int P, typename T, int PH>
 size_t face_lds_bytes(int C)
 {
@@ -780,9 +787,8 @@ size_t face_lds_bytes(int C)
     constexpr int PP = FacePad<P>::PP;
     const size_t hdr = (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16;
     const size_t Q = (size_t)C * F * (PP * K / P);
-    const size_t W = (size_t)(C + 1) * F * (PP * NP / P);
     const size_t NA = Fld<D, PH>::GRAD ? 4 : 2;
-    const size_t tot = (W > 5 * Q ? W : 5 * Q) + NA * Q;
+    const size_t tot = 5 * Q + NA * Q;
     return hdr + sizeof(T) * tot;
 }
 
