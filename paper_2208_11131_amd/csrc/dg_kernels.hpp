@@ -627,49 +627,51 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         d1p = Sx + Q;
     }
 
-    // point fluxes
+    // point fluxes: F = HLLC(u-, u+) - vis, vis = F_NS(u~, grad u~) + eps grad u~
+    //   (viscous / AV part from the recovered state, Sec. 3.2 and 4.1)
     const T gamma = (T)ph.gamma;
     const Tab<T> &tb = TabSel<T>::get(P);
     T *fb = (T *)a.fb + geo.fb_off[AX];
-    for (int q = tid; q < C * K; q += nt) {
-        const int c = q / K, k = q - c * K;
-        if (c >= nface) continue;
-        const int kp = ppos<P, PP>(k);
-        T uL[D + 2], uR[D + 2], Fh[D + 2];
+    auto viscous = [&](int c, int kp, T *vis) {
+        T ut[MAXF];
+        T g[D][MAXF];
+        constexpr int T1 = (AX == 0) ? 1 : 0;             // transverse axes, ascending
+        constexpr int T2 = (D == 3) ? ((AX == 2) ? 1 : 2) : 0;
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const int idx = (c * F + f) * NAF + kp;
+            ut[f] = utp[idx];
+            g[AX][f] = rnp[idx] * (T)ph.inv_fh;
+            g[T1][f] = d1p[idx] * (T)ph.two_over_h;
+            if (D == 3) g[T2][f] = d2p[idx] * (T)ph.two_over_h;
+        }
+        const Prim<D, T> s = primitives<D, T>(ut, gamma);
+#pragma unroll
+        for (int f = 0; f < D + 2; ++f) vis[f] = T(0);
+        if (PH == 1 || ph.ns_on) {
+            T fv[D + 2];
+            const NsGrad<D, T> ng = ns_grad<D, T>(ut, s, g);
+            ns_flux<D, T>(s, ng, AX, gamma, (T)ph.nu, (T)ph.kappa, fv);
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) vis[f] = fv[f];
+        }
+        if (PH == 2) {
+            const T cs = sqrt(gamma * s.p * s.ir);
+            const T eps = (T)ph.av_scale * clamp_alpha(ut[D + 2], (T)ph.alpha_max) * cs * (T)ph.eps_fac;
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) vis[f] += eps * g[AX][f];
+        }
+    };
+    auto riemann = [&](int c, int kp, T *Fh) {
+        T uL[D + 2], uR[D + 2];
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) {
             uL[f] = tLp[(c * F + f) * NAF + kp];
             uR[f] = tRp[(c * F + f) * NAF + kp];
         }
         hllc<D, T>(uL, uR, AX, gamma, Fh);
-        if (GRAD) {
-            T ut[MAXF];
-            T g[D][MAXF];
-            constexpr int T1 = (AX == 0) ? 1 : 0;             // transverse axes, ascending
-            constexpr int T2 = (D == 3) ? ((AX == 2) ? 1 : 2) : 0;
-#pragma unroll
-            for (int f = 0; f < F; ++f) {
-                const int idx = (c * F + f) * NAF + kp;
-                ut[f] = utp[idx];
-                g[AX][f] = rnp[idx] * (T)ph.inv_fh;
-                g[T1][f] = d1p[idx] * (T)ph.two_over_h;
-                if (D == 3) g[T2][f] = d2p[idx] * (T)ph.two_over_h;
-            }
-            const Prim<D, T> s = primitives<D, T>(ut, gamma);
-            if (PH == 1 || ph.ns_on) {
-                T fv[D + 2];
-                const NsGrad<D, T> ng = ns_grad<D, T>(ut, s, g);
-                ns_flux<D, T>(s, ng, AX, gamma, (T)ph.nu, (T)ph.kappa, fv);
-#pragma unroll
-                for (int f = 0; f < D + 2; ++f) Fh[f] -= fv[f];
-            }
-            if (PH == 2) {
-                const T cs = sqrt(gamma * s.p * s.ir);
-                const T eps = (T)ph.av_scale * clamp_alpha(ut[D + 2], (T)ph.alpha_max) * cs * (T)ph.eps_fac;
-#pragma unroll
-                for (int f = 0; f < D + 2; ++f) Fh[f] -= eps * g[AX][f];
-            }
-        }
+    };
+    auto store = [&](int c, int k, const T *Fh) {
         T gk = tb.g[k % P];
         if (D == 3) gk *= tb.g[k / P];
         int cf[3] = {co[0], co[1], co[2]};
@@ -680,6 +682,20 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         T *dst = fb + fi * (long long)(Fc * K) + k;
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) dst[f * K] = gk * Fh[f];
+    };
+    for (int q = tid; q < C * K; q += nt) {
+        const int c = q / K, k = q - c * K;
+        if (c >= nface) continue;
+        const int kp = ppos<P, PP>(k);
+        T Fh[D + 2];
+        riemann(c, kp, Fh);
+        if (GRAD) {
+            T vis[D + 2];
+            viscous(c, kp, vis);
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) Fh[f] -= vis[f];
+        }
+        store(c, k, Fh);
     }
 }
 
