@@ -442,7 +442,9 @@ dg_status launch(dg_ctx *c, int kind, const void *fn, dim3 grid, dim3 block, voi
             const size_t need = 2 * (size_t)(c->ev_used + 1);
             while (c->ev_pool->size() < need) {
                 hipEvent_t e;
-                if (!ok(hipEventCreate(&e))) return DG_EDEVICE;
+                // timing-only events: no system-scope fence (no cache writeback /
+                // invalidation between the kernels being measured)
+                if (!ok(hipEventCreateWithFlags(&e, hipEventDisableSystemFence))) return DG_EDEVICE;
                 c->ev_pool->push_back(e);
             }
             e0 = (*c->ev_pool)[2 * c->ev_used];
