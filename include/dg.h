@@ -177,10 +177,12 @@ dg_status dg_timing_read(dg_ctx *ctx, double *face_ms, long long *face_n, double
 
 /* ---------------------------------------------------------------------------
  * Batched ensembles: many independent boxes (own mesh size and order, same
- * dimension and physics) advanced together.  Boxes are grouped by order; each
- * group runs one grouped launch per kernel kind and RK stage over all of its
- * boxes (a device table maps flat blocks to (box, tile)), and the whole step
- * of every group is captured once into a hipGraph and replayed.
+ * dimension and physics) advanced together.  Boxes under 65536 cells are
+ * grouped by order; each group runs one grouped launch per kernel kind and RK
+ * stage over all of its boxes (a device table maps flat blocks to (box,
+ * tile)); larger boxes run their own kernels (they fill the device alone).
+ * The whole step of every box is captured once into a hipGraph and replayed.
+ * Every box gives the same bits as stepping it alone with dg_step_cfl.
  * ------------------------------------------------------------------------- */
 typedef struct dg_batch dg_batch;
 

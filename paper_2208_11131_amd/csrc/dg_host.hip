@@ -1032,6 +1032,7 @@ struct dg_batch {
     double cfl = 0.5;
     std::vector<dg_ctx *> box;
     std::vector<Group> groups;
+    std::vector<int> large;        // boxes stepped by their own kernels inside the step
     std::vector<double *> wptr;
     bool have_graph = false;
     hipGraph_t graph = nullptr;
@@ -1096,8 +1097,19 @@ int stage_table(int S, dgk::StageDesc *sd)
     return 5;
 }
 
+// Boxes with at least this many cells keep their own (fixed-tile) kernels
+// inside the batched step: they fill the device by themselves, and the grouped
+// kernels' per-block box lookup only pays off for the small, launch-bound ones.
+constexpr long long kBatchLargeCells = 65536;
+
 dg_status batch_enqueue(dg_batch *b, hipStream_t s)
 {
+    for (int i : b->large) {
+        dg_ctx *c = b->box[i];
+        dg_status st = run_cfl(c, b->wptr[i], nullptr, s);
+        if (st == DG_OK) st = rk_step(c, b->wptr[i], 0.0, c->scal, s);
+        if (st != DG_OK) return st;
+    }
     for (Group &g : b->groups) {
         const int n = (int)g.boxes.size();
         dgk::BoxDesc *d = g.d_desc;
@@ -1155,11 +1167,13 @@ dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, doub
             return st;
         }
     }
+    for (int i = 0; i < nbox; ++i)
+        if (b->box[i]->ncells >= kBatchLargeCells) b->large.push_back(i);
     for (int P = 1; P <= MAXP; ++P) {
         Group g;
         g.P = P;
         for (int i = 0; i < nbox; ++i)
-            if (orders[i] == P) g.boxes.push_back(i);
+            if (orders[i] == P && b->box[i]->ncells < kBatchLargeCells) g.boxes.push_back(i);
         if (g.boxes.empty()) continue;
         const dg_ctx *c0 = b->box[g.boxes[0]];
         g.ks = c0->ks;

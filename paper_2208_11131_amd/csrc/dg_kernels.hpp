@@ -744,12 +744,20 @@ __global__ void __launch_bounds__(NT) face_kernel_fixed(Phys ph, Geo geo, FaceAr
     face_dispatch<D, P, T, PH, C, NT>(ph, geo, a, smem, ax, bid);
 }
 
-// Index of the box owning flat block b of a grouped launch (uniform scan).
+// Index of the box owning flat block b of a grouped launch.
 __device__ __forceinline__ int owner_box(const BoxDesc *boxes, int nbox, long long b, int which)
 {
-    int i = 0;
-    while (i + 1 < nbox && boxes[i + 1].start[which] <= b) ++i;
-    return i;
+    // largest i with start[i] <= b (starts are non-decreasing, start[0] = 0):
+    // binary search, about log2(nbox) uniform loads
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boxes[mid].start[which] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 // Grouped face kernel: every box of one (dim, order) group; flat block index
