@@ -44,7 +44,7 @@ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 enum { M_B = 0, M_BT = 1, M_D = 2, M_DT = 3, M_BD = 4 };
 
-// Entry (k, i) of the operator applied by axis_pass: out_i = sum_k M(k, i) in_k.
+// Entry (k, i) of the operator of a line pass: out_i = sum_k M(k, i) in_k.
 template <int P, typename T, int MAT>
 __device__ __forceinline__ T mat(int k, int i)
 {
@@ -54,65 +54,6 @@ __device__ __forceinline__ T mat(int k, int i)
     if (MAT == M_D) return t.D[i][k];        // derivative at point i
     if (MAT == M_DT) return t.D[k][i];       // transpose of the derivative
     return t.Bd[k][i];                       // derivative of mode k at point i
-}
-
-// Apply a p x p operator along axis AX of ncell*NPER arrays of p^DA entries.
-// Array (c, f) starts at in + c*in_cs + f*p^DA (likewise out).  Each work item
-// is one line along AX: p loads, p*p FMAs with table operands, p stores.
-template <int P, int DA, int AX, typename T, int MAT, bool ACC, int NPER>
-__device__ __forceinline__ void axis_pass(const T *__restrict__ in, int in_cs, T *__restrict__ out, int out_cs,
-                                          int ncell)
-{
-    constexpr int NA = ipow(P, DA);
-    constexpr int NL = NA / P;
-    constexpr int S = ipow(P, AX);
-    const int nitems = ncell * NPER * NL;
-    for (int q = threadIdx.x; q < nitems; q += blockDim.x) {
-        const int cf = q / NL;
-        const int t = q - cf * NL;
-        const int c = cf / NPER;
-        const int f = cf - c * NPER;
-        const int lo = t % S, hi = t / S;
-        const int off = f * NA + lo + hi * S * P;
-        const T *pi = in + c * in_cs + off;
-        T *po = out + c * out_cs + off;
-        T x[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = pi[k * S];
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            T acc = ACC ? po[i * S] : T(0);
-#pragma unroll
-            for (int k = 0; k < P; ++k) acc = fma(mat<P, T, MAT>(k, i), x[k], acc);
-            po[i * S] = acc;
-        }
-    }
-}
-
-// Apply a p x p operator along axis AX of narr contiguous arrays of p^DA
-// entries.  Line q starts at (q / S) * S * p + q % S (S = p^AX): a couple of
-// integer operations per line; p loads, p*p FMAs with table operands, p stores.
-template <int P, int DA, int AX, typename T, int MAT, bool ACC>
-__device__ __forceinline__ void line_pass(const T *__restrict__ in, T *__restrict__ out, int narr)
-{
-    constexpr int NA = ipow(P, DA);
-    constexpr int S = ipow(P, AX);
-    const int nitems = narr * (NA / P);
-    for (int q = threadIdx.x; q < nitems; q += blockDim.x) {
-        const int off = (q / S) * (S * P) + (q % S);
-        const T *pi = in + off;
-        T *po = out + off;
-        T x[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = pi[k * S];
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            T acc = ACC ? po[i * S] : T(0);
-#pragma unroll
-            for (int k = 0; k < P; ++k) acc = fma(mat<P, T, MAT>(k, i), x[k], acc);
-            po[i * S] = acc;
-        }
-    }
 }
 
 // Padded point layout of one per-cell array: rows along x hold PP entries
@@ -1377,27 +1318,45 @@ __device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const C
     const int tid = threadIdx.x, nt = blockDim.x;
     const long long NC = geo.ncells;
     const long long c0 = tile * C;
+    constexpr int K = NP / P;
+    constexpr int NAP = Pad<P>::PP * K;      // padded per-cell array
+    const int CNP = C * NAP;
+    // LDS field-major [field][cell][padded point]
     double *X0 = (double *)smem;
-    double *X1 = X0 + C * Fc * NP;
-    double *red = X1 + C * Fc * NP;      // [2][nt]
-    // the first Fc fields of each cell, VW consecutive weights per access
-    constexpr int VW = ((Fc * NP) % 2 == 0 && FNP % 2 == 0) ? 2 : 1;
-    for (int g = tid; g < C * Fc * NP / VW; g += nt) {
-        const int i = g * VW;
-        const int c = i / (Fc * NP), r = i - c * (Fc * NP);
-        long long cc = c0 + c;
-        if (cc >= NC) cc = NC - 1;
-        const DV<VW> v = ldv<VW>(a.w + cc * FNP + r);
+    double *X1 = X0 + Fc * CNP;
+    double *red = X1 + Fc * CNP;         // [2][nt]
+    // values at the Gauss points of the Fc conserved fields: the pass along x
+    // reads each line's p modal weights straight from HBM, the others run in LDS
+    {
+        constexpr int VWL = (P % 2 == 0) ? 2 : 1;
+        for (int q = tid; q < Fc * C * K; q += nt) {
+            const int arr = q / K, t = q - arr * K;
+            const int f = arr / C, c = arr - f * C;
+            long long cc = c0 + c;
+            if (cc >= NC) cc = NC - 1;
+            const double *src = a.w + cc * FNP + f * NP + t * P;
+            double x[P];
 #pragma unroll
-        for (int h = 0; h < VW; ++h) X0[i + h] = v.x[h];
+            for (int k = 0; k < P; k += VWL) {
+                const DV<VWL> v = ldv<VWL>(src + k);
+#pragma unroll
+                for (int h = 0; h < VWL; ++h) x[k + h] = v.x[h];
+            }
+            const int o = pad_line_offset<P, D, 0>(q);
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) acc = fma(mat<P, double, M_B>(k, i), x[k], acc);
+                X1[o + i] = acc;
+            }
+        }
     }
     __syncthreads();
-    axis_pass<P, D, 0, double, M_B, false, Fc>(X0, Fc * NP, X1, Fc * NP, C);
-    __syncthreads();
-    axis_pass<P, D, 1, double, M_B, false, Fc>(X1, Fc * NP, X0, Fc * NP, C);
+    line_pass_pad<P, D, 1, double, M_B, false>(X1, X0, Fc * C);
     __syncthreads();
     if (D == 3) {
-        axis_pass<P, D, (D == 3 ? 2 : 0), double, M_B, false, Fc>(X0, Fc * NP, X1, Fc * NP, C);
+        line_pass_pad<P, D, (D == 3 ? 2 : 0), double, M_B, false>(X0, X1, Fc * C);
         __syncthreads();
     }
     const double *U = (D == 3) ? X1 : X0;
@@ -1407,7 +1366,7 @@ __device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const C
         if (c0 + c >= NC) continue;
         double u[D + 2];
 #pragma unroll
-        for (int f = 0; f < D + 2; ++f) u[f] = U[c * Fc * NP + f * NP + j];
+        for (int f = 0; f < D + 2; ++f) u[f] = U[f * CNP + c * NAP + ppos<P>(j)];
         const Prim<D, double> s = primitives<D, double>(u, ph.gamma);
         double v2 = 0.0;
 #pragma unroll
@@ -1456,8 +1415,8 @@ __global__ void __launch_bounds__(512) cfl_kernel_batched(const BoxDesc *boxes, 
 template <int D, int P>
 size_t cfl_lds_bytes(int C, int nt)
 {
-    constexpr int NP = ipow(P, D);
-    return sizeof(double) * ((size_t)2 * C * (D + 2) * NP + 2 * (size_t)nt);
+    constexpr int NAP = Pad<P>::PP * ipow(P, D - 1);   // padded per-cell array
+    return sizeof(double) * ((size_t)2 * C * (D + 2) * NAP + 2 * (size_t)nt);
 }
 
 // ---------------------------------------------------------------------------
