@@ -24,8 +24,10 @@ Extra objects on the JSON line:
   turbulence_3d  the 3D driven-turbulence box, 128^3, p = 4 (FP64), with its
                own roofline record;
   ensemble     48 independent 2D boxes (sides 32..512, orders 2..6) stepped by
-               grouped launches replayed from one hipGraph, against the same
-               steps issued box by box.
+               one captured hipGraph (grouped launches for the small boxes),
+               against the same steps issued box by box;
+  kh_order_sweep  the shear layer at every order p = 2..8, FP64 and FP32 bulk
+               (5 timed steps each), with the dominant kernel's roofline.
 """
 import argparse
 import hashlib
@@ -384,6 +386,21 @@ def main():
         print("bench: ensemble", file=sys.stderr, flush=True)
         line["ensemble"] = measure_ensemble(5, 1)
         torch.cuda.empty_cache()
+        if args.config == "kh":
+            print("bench: order sweep", file=sys.stderr, flush=True)
+            sweep = {}
+            for p in range(2, 9):
+                rec = {}
+                for prec in ("fp64", "fp32"):
+                    r = measure("kh", p, prec, 5, 2)
+                    d = r["kernels"][r["dominant"]]
+                    rec[prec] = {"value": r["value"], "ms_per_step": r["ms"] / 5,
+                                 "dominant": r["dominant"], "bound": d["bound"], "frac": d["frac"],
+                                 "stage_frac_hbm": r["stage"]["frac_hbm"]}
+                    del r
+                    torch.cuda.empty_cache()
+                sweep[str(p)] = rec
+            line["kh_order_sweep"] = sweep
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(desc, args.order, stages, dofs)
