@@ -128,7 +128,7 @@ def tune(configs, steps=3, log=sys.stderr):
 
 def write_table(rows, path):
     with open(path, "w") as fh:
-        fh.write("// Launch tiles chosen by paper_2208_11131_amd/tune.py (generated file).\n")
+        fh.write("// Launch tiles measured on the GPU (written by paper_2208_11131_amd/tune.py).\n")
         fh.write("// {dim, order, precision (0 FP64, 1 FP32 bulk), physics (0 Euler, 1 NS, 2 AV),\n")
         fh.write("//  forcing, vol cells, vol threads, face pencil, face threads}\n")
         for r in rows:
