@@ -393,14 +393,14 @@ def _sampled_cells(ncells, nsample, rng):
     return np.array(sorted(idx), dtype=np.int64)
 
 
-@pytest.mark.parametrize("cfg", ["kh_p8", "sod_p6", "turb_p4"])
+@pytest.mark.parametrize("cfg", ["kh_p4", "kh_p8", "sod_p6", "turb_p4"])
 def test_full_size_sampled(cfg):
     """Full-size states in the benchmark's launch configuration: the GPU RHS on
     the whole mesh against the oracle at sampled cells (incl. both ends)."""
     rng = np.random.default_rng(2208)
     say("full size", cfg)
-    if cfg == "kh_p8":
-        order, n = 8, (256, 512)
+    if cfg in ("kh_p4", "kh_p8"):
+        order, n = (4 if cfg == "kh_p4" else 8), (256, 512)
         w = W.kelvin_helmholtz(order, *n, device="cuda")
         gpu, ref = pair(2, n, order, gamma=5.0 / 3.0, nu=1e-4)
     elif cfg == "sod_p6":
@@ -419,6 +419,25 @@ def test_full_size_sampled(cfg):
     cells = _sampled_cells(ref.ncells, 24, rng)
     Lr = ref.rhs_cells(wh, cells, R_prev=np.zeros(ref.ncells) if ref.av is not None else None)
     assert rhs_err(L[cells], Lr, wh, ref.dim, cfl_rate(ref, wh), mom_scale=momentum_scale(ref, wh)) <= 1e-12
+
+
+def test_full_size_headline_step():
+    """The benchmark's step itself: one dg_step_cfl (device CFL reduction,
+    five SSPRK(5,4) stages) of the full 256 x 512, p = 4 shear layer with the
+    default (tuned, fixed-tile) kernels, against one oracle step with its own
+    CFL step size, on every cell."""
+    order, n = 4, (256, 512)
+    say("full size headline step")
+    w = W.kelvin_helmholtz(order, *n, device="cuda")
+    gpu, ref = pair(2, n, order, gamma=5.0 / 3.0, nu=1e-4)
+    w0 = w.cpu().numpy()
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gpu.step_cfl(w, dt_dev)
+    assert gpu.check() == 0
+    dtr = ref.max_dt(w0)[0]
+    assert abs(float(dt_dev) - dtr) <= 1e-14 * dtr
+    wr, _ = ref.step(w0, float(dt_dev))
+    assert state_err(w.cpu().numpy(), wr, 2, mom_scale=momentum_scale(ref, wr)) <= 1e-12
 
 
 def test_fp32_bulk_density_wave_run():
