@@ -862,10 +862,18 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     //    along x reads each line's p modal weights (contiguous in HBM)
     //    straight from the state or forcing arrays, so the weights never
     //    pass through LDS; the same FMA chain as the LDS passes.
+    // With a fixed tile, line q = tid + r NT of this pass (r < KEEP) is also
+    // line r of the final projection / RK pass of this thread: its FP64
+    // weights are kept in registers for the RK combination (no second read).
+    // (2D only: in 3D the kept registers pushed the forced kernel into SGPR
+    // spills and were measured slower)
+    constexpr int KEEP0 = (CC > 0 && NTC > 0 && D == 2) ? (CC * F * K + NTC - 1) / NTC : 0;
+    constexpr int KEEP = (KEEP0 * P <= 8) ? KEEP0 : 0;
+    double pcu[KEEP > 0 ? KEEP : 1][P];
     {
         constexpr int VWL = (P % 2 == 0) ? 2 : 1;       // state weights per load
         const int nitems = Fx * C * K;                  // K = p^(d-1) lines per array
-        for (int q = tid; q < nitems; q += nt) {
+        auto first_line = [&](int q, double *keep) {
             const int arr = q / K, t = q - arr * K;
             const int f = arr / C, c = arr - f * C;
             long long cc = c0 + c;
@@ -877,7 +885,10 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
                 for (int k = 0; k < P; k += VWL) {
                     const DV<VWL> v = ldv<VWL>(src + k);
 #pragma unroll
-                    for (int h = 0; h < VWL; ++h) x[k + h] = (T)v.x[h];
+                    for (int h = 0; h < VWL; ++h) {
+                        x[k + h] = (T)v.x[h];
+                        if (keep) keep[k + h] = v.x[h];
+                    }
                 }
             } else {
                 const double *src = a.forcing + cc * (D * NP) + (f - F) * NP + t * P;
@@ -892,7 +903,11 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
                 for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_B>(k, i), x[k], acc);
                 X1[o + i] = acc;
             }
-        }
+        };
+#pragma unroll
+        for (int r = 0; r < KEEP; ++r)
+            if (tid + r * nt < nitems) first_line(tid + r * nt, pcu[r]);
+        for (int q = tid + KEEP * nt; q < nitems; q += nt) first_line(q, nullptr);
     }
     __syncthreads();
     line_pass_pad<P, D, 1, T, M_B, false, NTC>(X1, X0, Fx * C);
@@ -999,8 +1014,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     constexpr int NDT = FUSED ? (CC * Fc * K + NTC - 1) / NTC : 1;   // D^T lines per thread
     // lines of the final (x) projection pass per thread, and how many of them
     // get their RK inputs read early (p doubles per array per line)
-    constexpr int NBL0 = FUSED ? (CC * F * K + NTC - 1) / NTC : 0;
-    constexpr int NBL = (NBL0 * P <= 8) ? NBL0 : 0;
+    constexpr int NBL = KEEP;                      // their cur weights are already in pcu
     const int nlift = C * Fc * K;
     auto lift_load = [&](int q, T *Fl, T *Fu) {
         const bool act = q < nlift;
@@ -1041,7 +1055,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     constexpr int VWL = (P % 2 == 0) ? 2 : 1;      // weights per access along a line
     const int nx = F * C * K;                      // lines of the final projection pass
     // RK inputs of a final-pass line: p consecutive weights of cur / base / x2
-    auto rk_load = [&](int q, double *cu, double *ba, double *x2) {
+    auto rk_load = [&](int q, double *cu, double *ba, double *x2, bool with_cur) {
         const int arr = q / K, t = q - arr * K;
         const int f = arr / C, c = arr - f * C;
         const long long cc = c0 + c;
@@ -1050,20 +1064,20 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
 #pragma unroll
         for (int k = 0; k < P; k += VWL) {
             const DV<VWL> zc = zdv<VWL>();
-            const DV<VWL> vc = ok ? ldv<VWL>(a.cur + gi + k) : zc;
+            const DV<VWL> vc = (ok && with_cur) ? ldv<VWL>(a.cur + gi + k) : zc;
             const DV<VWL> vb = (ok && a.base) ? ldv<VWL>(a.base + gi + k) : zc;
             const DV<VWL> vx = (ok && a.x2) ? ldv<VWL>(a.x2 + gi + k) : zc;
 #pragma unroll
             for (int h = 0; h < VWL; ++h) {
-                cu[k + h] = vc.x[h];
+                if (with_cur) cu[k + h] = vc.x[h];
                 ba[k + h] = vb.x[h];
                 x2[k + h] = vx.x[h];
             }
         }
     };
-    double pcu[NBL > 0 ? NBL : 1][P], pba[NBL > 0 ? NBL : 1][P], px2[NBL > 0 ? NBL : 1][P];
+    double pba[NBL > 0 ? NBL : 1][P], px2[NBL > 0 ? NBL : 1][P];
 #pragma unroll
-    for (int r = 0; r < NBL; ++r) rk_load(tid + r * nt, pcu[r], pba[r], px2[r]);
+    for (int r = 0; r < NBL; ++r) rk_load(tid + r * nt, pcu[r], pba[r], px2[r], false);
 
     // 5.-6. Q += sum_a [D_a^T (w f_a) + surface lift of the two a-faces], axis by axis
     if constexpr (FUSED) {
@@ -1174,7 +1188,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         if (tid + r * nt < nx) xpass_rk(tid + r * nt, pcu[r], pba[r], px2[r]);
     for (int q = tid + NBL * nt; q < nx; q += nt) {
         double cu[P], ba[P], x2[P];
-        rk_load(q, cu, ba, x2);
+        rk_load(q, cu, ba, x2, true);
         xpass_rk(q, cu, ba, x2);
     }
     if (bad) atomicOr(blkflag, bad);
