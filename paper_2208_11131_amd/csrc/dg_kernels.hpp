@@ -4,18 +4,24 @@
 // its own copy of the per-order tables in __constant__ memory (uploaded by
 // the host runtime through the unit's dgk_upload_* entry).
 //
-// Work decomposition (one HIP thread block = a tile of whole cells or faces,
-// all intermediate data in LDS):
-//   face kernel    per face of direction a = blockIdx.y: traces of both
-//                  cells, HLLC, and (viscous/AV) the interface recovery of
-//                  Sec. 3.2 with the Navier-Stokes/AV flux; writes one
-//                  single-valued flux per face point to the face buffer.
+// Work decomposition (one HIP thread block = a tile of whole cells or a pencil
+// of faces; intermediates in LDS, the state read from and written to HBM by
+// the passes that need it):
+//   face kernel    a pencil of faces of direction a = blockIdx.y: traces of
+//                  both cells (normal lines read from HBM), HLLC, and
+//                  (viscous/AV) the interface recovery of Sec. 3.2 with the
+//                  Navier-Stokes/AV flux; one single-valued flux per face
+//                  point to the face buffer.
 //   volume kernel  per cell: modal -> Gauss-point values by sum factorisation
-//                  (one p x p operator per axis), collocation gradients,
-//                  point fluxes and sources, D^T and the face lift in point
-//                  space, point -> modal projection, prefactor 2^(1-d)/h,
-//                  and the SSP-RK stage combination in FP64.
+//                  (one p x p operator per axis, the first reading HBM),
+//                  collocation gradients, point fluxes and sources, D^T fused
+//                  with the face lift in point space, point -> modal
+//                  projection whose last pass is fused with the FP64 SSP-RK
+//                  stage combination (prefactor 2^(1-d)/h) and write-back.
 //   cfl kernel     maxima of c_s and |v| over all volume Gauss points.
+// Fixed-tile variants (tile and forcing as template parameters) exist for
+// the tuned tiles; every variant rounds identically (contraction is limited
+// to single expressions by the build).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -794,9 +800,9 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
 
     // LDS, field-major: Ub [field][cell][point] (point values, then sources),
     // G [axis][field][cell][point] (gradients, then fluxes); points in the
-    // padded layout of Pad<P>.  The modal load and the ping-pong buffer of the
-    // contraction passes live in G's space (D F >= F + D arrays), which is
-    // free outside the gradient / flux phases.
+    // padded layout of Pad<P>.  The ping-pong buffer of the contraction
+    // passes lives in G's space (D F >= F + D arrays), which is free outside
+    // the gradient / flux phases.
     long long *fidx = (long long *)smem;      // [C][D][2] lower/upper face index per axis
     double *cellv = (double *)(fidx + 2 * D * C);   // [C]: wiggle source
     double *cmean = cellv + C;                // [C][D+2]: new cell means (checks)
