@@ -75,6 +75,13 @@ struct FaceArgs {
     const double *w;
     void *fb;
     int faces_per_block;
+    // CFL finalize folded into this launch (cfl_part != null): block (0, 0)
+    // reduces the CFL kernel's per-block maxima and writes dt
+    const double *cfl_part;
+    double *cfl_res;       // [0] dt, [1] c_max, [2] v_max
+    double *cfl_dt_copy;   // optional second copy of dt
+    double cfl_num;        // f_CFL h / (2 p)
+    int cfl_nblk;
 };
 
 struct CflArgs {

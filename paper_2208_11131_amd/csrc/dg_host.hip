@@ -362,6 +362,8 @@ struct dg_ctx {
     KernelSet ks, ks64;
     const void *vol_fixed[2];   // fixed-tile volume kernels (no forcing / forcing) for the tile in use, or null
     const void *face_fixed;     // fixed-tile face kernel for the tile in use, or null
+    bool fin_pending;           // the next face launch carries the CFL finalize
+    double *fin_dt_copy;        // its optional second copy of dt
     int vol_C, vol_T, face_C, face_T, cfl_C, cfl_T, cfl_blocks;
     size_t vol_lds, vol_lds_forced, face_lds, cfl_lds;
     int stages;
@@ -468,6 +470,19 @@ dg_status stage(dg_ctx *c, dgk::VolArgs va, hipStream_t s)
     fa.w = va.cur;
     fa.fb = c->fb;
     fa.faces_per_block = c->face_C;
+    fa.cfl_part = nullptr;
+    fa.cfl_res = nullptr;
+    fa.cfl_dt_copy = nullptr;
+    fa.cfl_num = 0.0;
+    fa.cfl_nblk = 0;
+    if (c->fin_pending) {      // the CFL finalize of this step rides on this launch
+        fa.cfl_part = c->cfl_part;
+        fa.cfl_res = c->scal;
+        fa.cfl_dt_copy = c->fin_dt_copy;
+        fa.cfl_num = c->cfl * c->ph.h / (2.0 * c->P);
+        fa.cfl_nblk = c->cfl_blocks;
+        c->fin_pending = false;
+    }
     void *fargs[] = {&c->ph, &c->geo, &fa};
     dim3 fg((unsigned)dgk::face_pencils(c->geo, c->dim, c->face_C), (unsigned)c->dim);
     dg_status st = launch(c, 0, c->face_fixed ? c->face_fixed : c->ks.face, fg, dim3(c->face_T), fargs,
@@ -491,7 +506,10 @@ dgk::VolArgs blank_args()
     return v;
 }
 
-dg_status run_cfl(dg_ctx *c, const double *w, double *dt_copy, hipStream_t s)
+// CFL reduction of w.  finalize_now: also launch the one-block finalize (dt in
+// c->scal on return to the stream); otherwise the finalize is carried by the
+// next face launch of this context (the first stage of the step).
+dg_status run_cfl(dg_ctx *c, const double *w, double *dt_copy, hipStream_t s, bool finalize_now = true)
 {
     dgk::CflArgs ca;
     ca.w = w;
@@ -501,6 +519,11 @@ dg_status run_cfl(dg_ctx *c, const double *w, double *dt_copy, hipStream_t s)
     dim3 g((unsigned)c->cfl_blocks);
     dg_status st = launch(c, 2, c->ks64.cfl, g, dim3(c->cfl_T), args, c->cfl_lds, s);
     if (st != DG_OK) return st;
+    if (!finalize_now) {
+        c->fin_pending = true;
+        c->fin_dt_copy = dt_copy;
+        return DG_OK;
+    }
     double num = c->cfl * c->ph.h / (2.0 * c->P);
     const double *part = c->cfl_part;
     int nblk = c->cfl_blocks;
@@ -770,7 +793,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         c->face_T = te->face_T;
     else
         c->face_T = std::min(512, std::max(64, roundup(c->face_C * c->K, 64)));
-    c->face_lds = c->ks.face_lds(c->face_C);
+    c->face_lds = std::max<size_t>(c->ks.face_lds(c->face_C), 256);   // >= the CFL finalize's 16 doubles
     c->cfl_C = std::max(1, 256 / c->NP);
     c->cfl_T = 256;
     while (c->cfl_C > 1 && c->ks64.cfl_lds(c->cfl_C, c->cfl_T) > 64 * 1024) --c->cfl_C;
@@ -910,9 +933,10 @@ dg_status dg_step_cfl(dg_ctx *c, double *w, double *dt_dev, void *stream)
 {
     if (!c || !w || !aligned16(w)) return DG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    dg_status st = run_cfl(c, w, dt_dev, s);
-    if (st != DG_OK) return st;
-    return rk_step(c, w, 0.0, c->scal, s);
+    dg_status st = run_cfl(c, w, dt_dev, s, false);
+    if (st == DG_OK) st = rk_step(c, w, 0.0, c->scal, s);
+    c->fin_pending = false;
+    return st;
 }
 
 dg_status dg_max_dt(dg_ctx *c, const double *w, double *dt_out, double *cmax_out, double *vmax_out, void *stream)
@@ -1106,8 +1130,9 @@ dg_status batch_enqueue(dg_batch *b, hipStream_t s)
 {
     for (int i : b->large) {
         dg_ctx *c = b->box[i];
-        dg_status st = run_cfl(c, b->wptr[i], nullptr, s);
+        dg_status st = run_cfl(c, b->wptr[i], nullptr, s, false);
         if (st == DG_OK) st = rk_step(c, b->wptr[i], 0.0, c->scal, s);
+        c->fin_pending = false;
         if (st != DG_OK) return st;
     }
     for (Group &g : b->groups) {

@@ -48,6 +48,9 @@ struct TabSel<float> {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
+// max that propagates NaN (order independent)
+__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
 enum { M_B = 0, M_BT = 1, M_D = 2, M_DT = 3, M_BD = 4 };
 
 // Entry (k, i) of the operator of a line pass: out_i = sum_k M(k, i) in_k.
@@ -667,10 +670,52 @@ __device__ __forceinline__ void face_dispatch(const Phys &ph, const Geo &geo, co
         face_body<D, P, (D == 3 ? 2 : 0), T, PH, CC, NTC>(ph, geo, a, smem, pen);
 }
 
+// The CFL finalize carried by a face launch: block (0, 0) reduces the CFL
+// kernel's per-block (c_s, |v|) maxima (wave shuffles, then 16 doubles of
+// LDS across the waves) and writes dt = f_CFL h / (2 p (c_max + v_max)).
+// The next kernel on the stream (the volume kernel of the same stage) reads it.
+__device__ __forceinline__ void face_cfl_finalize(const FaceArgs &a, unsigned char *smem)
+{
+    if (!a.cfl_part || blockIdx.x != 0 || blockIdx.y != 0) return;
+    const int nt = blockDim.x;
+    const double2 *pp = (const double2 *)a.cfl_part;
+    double c = 0.0, v = 0.0;
+#pragma unroll 4
+    for (int b = threadIdx.x; b < a.cfl_nblk; b += nt) {
+        const double2 x = pp[b];
+        c = nanmax(c, x.x);
+        v = nanmax(v, x.y);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        c = nanmax(c, __shfl_xor(c, off));
+        v = nanmax(v, __shfl_xor(v, off));
+    }
+    double *red = (double *)smem;
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * (threadIdx.x >> 6)] = c;
+        red[2 * (threadIdx.x >> 6) + 1] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nt / 64; ++w) {
+            c = nanmax(c, red[2 * w]);
+            v = nanmax(v, red[2 * w + 1]);
+        }
+        const double dt = a.cfl_num / (c + v);
+        a.cfl_res[0] = dt;
+        a.cfl_res[1] = c;
+        a.cfl_res[2] = v;
+        if (a.cfl_dt_copy) a.cfl_dt_copy[0] = dt;
+    }
+    __syncthreads();   // the face work reuses the LDS
+}
+
 template <int D, int P, typename T, int PH>
 __global__ void __launch_bounds__(512) face_kernel(Phys ph, Geo geo, FaceArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    face_cfl_finalize(a, smem);
     const int ax = blockIdx.y;
     const unsigned bid = xcd_block(blockIdx.x, gridDim.x);
     if ((long long)bid >= pencils(geo, ax, a.faces_per_block)) return;
@@ -685,6 +730,7 @@ __global__ void __launch_bounds__(NT) face_kernel_fixed(Phys ph, Geo geo, FaceAr
 {
     extern __shared__ __align__(16) unsigned char smem[];
     if (a.faces_per_block != C) return;   // host selection error
+    face_cfl_finalize(a, smem);
     const int ax = blockIdx.y;
     const unsigned bid = xcd_block(blockIdx.x, gridDim.x);
     if ((long long)bid >= pencils(geo, ax, C)) return;
@@ -721,6 +767,7 @@ __device__ __forceinline__ void face_batched_body(const BoxDesc *boxes, int nbox
     a.w = boxes[i].reg[stage_cur];
     a.fb = boxes[i].fb;
     a.faces_per_block = boxes[i].faces_per_block;
+    a.cfl_part = nullptr;
     if (CC > 0 && a.faces_per_block != CC) return;   // host selection error
     long long loc = b - boxes[i].start[1];
     for (int ax = 0; ax < D; ++ax) {
@@ -1325,7 +1372,6 @@ size_t vol_lds_bytes(int C, int Fx)
 // CFL kernel: maxima of c_s and |v| over the volume Gauss points (eq. timestep)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
 template <int D, int P, int PH>
 __device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const CflArgs &a, unsigned char *smem,
