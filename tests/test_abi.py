@@ -66,3 +66,16 @@ def test_init_rejects_invalid_arguments(case):
     assert r == dg.DG_EINVAL and not ctx.value
     assert dg.lib().dg_rhs(None, None, None, None) == dg.DG_EINVAL
     assert dg.lib().dg_step(None, None, 1.0, None) == dg.DG_EINVAL
+
+
+def test_init_rejects_meshes_beyond_the_index_limit():
+    """Cell and face indices are 32-bit on the device: meshes whose face
+    spaces exceed 2^31 - 1 entries are refused before any device call, so
+    this runs without a GPU."""
+    if not os.path.exists(dg.LIB_PATH):
+        pytest.skip("library not built")
+    for dim, n in ((2, (46341, 46341)), (3, (1291, 1291, 1291))):   # (n + 1)^d > 2^31 - 1
+        m = dg.make_mesh(dim, n)
+        ctx = ctypes.c_void_p()
+        r = dg.lib().dg_init(ctypes.byref(m), 1, 1.4, 0.0, 0.0, None, None, ctypes.byref(ctx))
+        assert r == dg.DG_EINVAL and not ctx.value
