@@ -364,7 +364,9 @@ struct dg_ctx {
     const void *face_fixed;     // fixed-tile face kernel for the tile in use, or null
     bool fin_pending;           // the next face launch carries the CFL finalize
     double *fin_dt_copy;        // its optional second copy of dt
-    int vol_C, vol_T, face_C, face_T, cfl_C, cfl_T, cfl_blocks;
+    int vol_C, vol_T, face_C, face_T, cfl_C, cfl_T;
+    int cfl_tiles;                 // tiles of cfl_C cells (one block each in a grouped launch)
+    int cfl_blocks;                // blocks (= partials) of a single-box CFL launch, at most kCflBlocks
     size_t vol_lds, vol_lds_forced, face_lds, cfl_lds;
     int stages;
     double *reg[3];
@@ -372,7 +374,7 @@ struct dg_ctx {
     size_t fb_bytes;
     double *R[2];
     int rpar;
-    double *cfl_part;              // [cfl_blocks][2]
+    double *cfl_part;              // [cfl_tiles][2]
     double *scal;                  // [0] dt, [1] cmax, [2] vmax, [3..] totals
     int *flag;
     double *tot_part;
@@ -430,6 +432,10 @@ const void *get_face_fixed(int dim, int prec, int P, int phys, int C, int NT, in
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
+
+// Blocks of a single-box CFL launch (each loops over tiles): bounds the
+// partial maxima the finalize reads, whatever the mesh size.
+constexpr int kCflBlocks = 4096;
 
 constexpr long long EV_MAX = 16384;
 
@@ -798,7 +804,8 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     c->cfl_T = 256;
     while (c->cfl_C > 1 && c->ks64.cfl_lds(c->cfl_C, c->cfl_T) > 64 * 1024) --c->cfl_C;
     c->cfl_lds = c->ks64.cfl_lds(c->cfl_C, c->cfl_T);
-    c->cfl_blocks = (int)((c->ncells + c->cfl_C - 1) / c->cfl_C);
+    c->cfl_tiles = (int)((c->ncells + c->cfl_C - 1) / c->cfl_C);
+    c->cfl_blocks = std::min(c->cfl_tiles, kCflBlocks);
     if (c->face_lds > LDS_MAX || c->cfl_lds > LDS_MAX) {
         delete c;
         return DG_EUNSUPPORTED;
@@ -827,7 +834,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
             good = ok(hipMalloc(&c->R[i], c->ncells * sizeof(double)));
             good = good && ok(hipMemset(c->R[i], 0, c->ncells * sizeof(double)));
         }
-    good = good && ok(hipMalloc(&c->cfl_part, (size_t)c->cfl_blocks * 2 * sizeof(double)));
+    good = good && ok(hipMalloc(&c->cfl_part, (size_t)c->cfl_tiles * 2 * sizeof(double)));
     good = good && ok(hipMalloc(&c->scal, 16 * sizeof(double)));
     good = good && ok(hipMalloc(&c->flag, sizeof(int)));
     good = good && ok(hipMemset(c->flag, 0, sizeof(int)));
@@ -1249,7 +1256,7 @@ dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, doub
                 nf += np;
             }
             d.nblocks[1] = nf;
-            d.nblocks[2] = c->cfl_blocks;
+            d.nblocks[2] = c->cfl_tiles;
             for (int k = 0; k < 3; ++k) {
                 d.start[k] = g.nblk[k];
                 g.nblk[k] += d.nblocks[k];

@@ -1373,9 +1373,12 @@ size_t vol_lds_bytes(int C, int Fx)
 // ---------------------------------------------------------------------------
 
 
+// Per-thread maxima of c_s and |v| over the Gauss points of one tile of C
+// cells (accumulated into cmax / vmax; ends with a barrier, so the block can
+// go on with another tile).
 template <int D, int P, int PH>
-__device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const CflArgs &a, unsigned char *smem,
-                                         long long tile)
+__device__ __forceinline__ void cfl_tile(const Phys &ph, const Geo &geo, const CflArgs &a, unsigned char *smem,
+                                         long long tile, double &cmax, double &vmax)
 {
     constexpr int NP = ipow(P, D);
     constexpr int Fc = D + 2;
@@ -1390,7 +1393,6 @@ __device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const C
     // LDS field-major [field][cell][padded point]
     double *X0 = (double *)smem;
     double *X1 = X0 + Fc * CNP;
-    double *red = X1 + Fc * CNP;         // [2][nt]
     // values at the Gauss points of the Fc conserved fields: the pass along x
     // reads each line's p modal weights straight from HBM, the others run in LDS
     {
@@ -1426,7 +1428,6 @@ __device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const C
         __syncthreads();
     }
     const double *U = (D == 3) ? X1 : X0;
-    double cmax = 0.0, vmax = 0.0;
     for (int q = tid; q < C * NP; q += nt) {
         const int c = q / NP, j = q - c * NP;
         if (c0 + c >= NC) continue;
@@ -1440,6 +1441,13 @@ __device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const C
         cmax = nanmax(cmax, sqrt(ph.gamma * s.p * s.ir));   // NaN propagates into dt
         vmax = nanmax(vmax, sqrt(v2));
     }
+    __syncthreads();
+}
+
+// Block maxima of the per-thread values into part[2 idx], part[2 idx + 1].
+__device__ __forceinline__ void cfl_block_store(double *part, long long idx, double *red, double cmax, double vmax)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
     red[tid] = cmax;
     red[nt + tid] = vmax;
     __syncthreads();
@@ -1451,16 +1459,29 @@ __device__ __forceinline__ void cfl_body(const Phys &ph, const Geo &geo, const C
         __syncthreads();
     }
     if (tid == 0) {
-        a.part[2 * tile] = red[0];
-        a.part[2 * tile + 1] = red[nt];
+        part[2 * idx] = red[0];
+        part[2 * idx + 1] = red[nt];
     }
 }
 
+// LDS scratch of the block reduction, after the tile arrays.
+template <int D, int P>
+__device__ __forceinline__ double *cfl_red(unsigned char *smem, int C)
+{
+    return (double *)smem + 2 * (D + 2) * C * Pad<P>::PP * ipow(P, D - 1);
+}
+
+// Single-box CFL kernel: each block loops over the tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ... and writes one partial, so the number of
+// partials (the grid) stays bounded for any mesh.
 template <int D, int P, int PH>
 __global__ void __launch_bounds__(512) cfl_kernel(Phys ph, Geo geo, CflArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    cfl_body<D, P, PH>(ph, geo, a, smem, blockIdx.x);
+    const long long ntiles = (geo.ncells + a.cells_per_block - 1) / a.cells_per_block;
+    double cmax = 0.0, vmax = 0.0;
+    for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) cfl_tile<D, P, PH>(ph, geo, a, smem, t, cmax, vmax);
+    cfl_block_store(a.part, blockIdx.x, cfl_red<D, P>(smem, a.cells_per_block), cmax, vmax);
 }
 
 template <int D, int P, int PH>
@@ -1475,7 +1496,9 @@ __global__ void __launch_bounds__(512) cfl_kernel_batched(const BoxDesc *boxes, 
     a.w = boxes[i].reg[0];
     a.part = boxes[i].cfl_part;
     a.cells_per_block = boxes[i].cfl_cells;
-    cfl_body<D, P, PH>(ph, geo, a, smem, b - boxes[i].start[2]);
+    double cmax = 0.0, vmax = 0.0;
+    cfl_tile<D, P, PH>(ph, geo, a, smem, b - boxes[i].start[2], cmax, vmax);
+    cfl_block_store(a.part, b - boxes[i].start[2], cfl_red<D, P>(smem, a.cells_per_block), cmax, vmax);
 }
 
 template <int D, int P>
