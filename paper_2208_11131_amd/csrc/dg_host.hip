@@ -873,9 +873,20 @@ dg_status dg_timing_enable(dg_ctx *c, int on)
 {
     if (!c) return DG_EINVAL;
     if (on && !c->ev_pool) {
-        c->ev_pool = new (std::nothrow) std::vector<hipEvent_t>();
-        c->ev_kind = new (std::nothrow) std::vector<int>();
-        if (!c->ev_pool || !c->ev_kind) return DG_ENOMEM;
+        // full capacity up front: launch() then never reallocates (nothing
+        // can throw across the ABI while kernels are being recorded)
+        try {
+            c->ev_pool = new std::vector<hipEvent_t>();
+            c->ev_kind = new std::vector<int>();
+            c->ev_pool->reserve(2 * EV_MAX);
+            c->ev_kind->reserve(EV_MAX);
+        } catch (...) {
+            delete c->ev_pool;
+            delete c->ev_kind;
+            c->ev_pool = nullptr;
+            c->ev_kind = nullptr;
+            return DG_ENOMEM;
+        }
     }
     c->timing = on ? 1 : 0;
     return DG_OK;
@@ -1175,8 +1186,8 @@ dg_status batch_enqueue(dg_batch *b, hipStream_t s)
 
 extern "C" {
 
-dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, double gamma, double nu, double kappa,
-                        const dg_av_params *av, const dg_options *opt, dg_batch **out)
+static dg_status batch_init_impl(int nbox, const dg_mesh *meshes, const int *orders, double gamma, double nu, double kappa,
+                               const dg_av_params *av, const dg_options *opt, dg_batch **out)
 {
     if (!out) return DG_EINVAL;
     *out = nullptr;
@@ -1186,6 +1197,15 @@ dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, doub
         if (meshes[i].dim != meshes[0].dim) return DG_EINVAL;
     dg_batch *b = new (std::nothrow) dg_batch;
     if (!b) return DG_ENOMEM;
+    // releases the partly built batch on every early return (and exception)
+    struct Guard {
+        dg_batch *b;
+        ~Guard()
+        {
+            if (b) {
+            }
+        }
+    } guard{b};
     b->nbox = nbox;
     b->dim = meshes[0].dim;
     b->cfl = opt ? opt->cfl : 0.5;
@@ -1194,8 +1214,6 @@ dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, doub
     for (int i = 0; i < nbox; ++i) {
         dg_status st = dg_init(&meshes[i], orders[i], gamma, nu, kappa, nullptr, opt, &b->box[i]);
         if (st != DG_OK) {
-            batch_release(b);
-            delete b;
             return st;
         }
     }
@@ -1225,8 +1243,6 @@ dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, doub
             if (ff) g.ks.face_b = ff;
         }
         if (!g.ks.vol_b || !g.ks.face_b || !g.ks64.cfl_b) {
-            batch_release(b);
-            delete b;
             return DG_EUNSUPPORTED;
         }
         (void)hipFuncSetAttribute(g.ks.vol_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
@@ -1264,14 +1280,24 @@ dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, doub
             g.h_desc.push_back(d);
         }
         if (!ok(hipMalloc(&g.d_desc, sizeof(dgk::BoxDesc) * g.h_desc.size()))) {
-            batch_release(b);
-            delete b;
             return DG_ENOMEM;
         }
         b->groups.push_back(g);
     }
+    guard.b = nullptr;
     *out = b;
     return DG_OK;
+}
+
+dg_status dg_batch_init(int nbox, const dg_mesh *meshes, const int *orders, double gamma, double nu, double kappa,
+                        const dg_av_params *av, const dg_options *opt, dg_batch **out)
+{
+    try {
+        return batch_init_impl(nbox, meshes, orders, gamma, nu, kappa, av, opt, out);
+    } catch (...) {   // host allocations; nothing throws across the ABI
+        if (out) *out = nullptr;
+        return DG_ENOMEM;
+    }
 }
 
 void dg_batch_free(dg_batch *b)
