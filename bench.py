@@ -26,6 +26,8 @@ Extra objects on the JSON line:
   ensemble     48 independent 2D boxes (sides 32..512, orders 2..6) stepped by
                one captured hipGraph (grouped launches for the small boxes),
                against the same steps issued box by box;
+  sod_av_2d    the AV shock tube, 1024 x 128, p = 6 (Euler + artificial
+               viscosity, outflow in x), FP64;
   kh_order_sweep  the shear layer at every order p = 2..8, FP64 and FP32 bulk
                (5 timed steps each), with the dominant kernel's roofline.
 """
@@ -386,6 +388,16 @@ def main():
                                                                 if k != r3["dominant"]}},
                                  "stage_roofline": r3["stage"]}
         del r3
+        torch.cuda.empty_cache()
+        print("bench: shock tube (AV)", file=sys.stderr, flush=True)
+        rs = measure("sod", 6, "fp64", 5, 1)
+        ds = rs["kernels"][rs["dominant"]]
+        line["sod_av_2d"] = {"value": rs["value"], "ms_per_step": rs["ms"] / 5, "config": rs["desc"],
+                             "roofline": {"kernel": rs["dominant"], "bound": ds["bound"], "achieved": ds["achieved"],
+                                          "peak": ds["peak"], "unit": ds["unit"], "frac": ds["frac"],
+                                          "avg_us": ds["avg_us"]},
+                             "stage_roofline": rs["stage"]}
+        del rs
         torch.cuda.empty_cache()
         print("bench: ensemble", file=sys.stderr, flush=True)
         line["ensemble"] = measure_ensemble(5, 1)
