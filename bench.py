@@ -18,8 +18,8 @@ Extra objects on the JSON line:
   stage_roofline  the whole stage (all kernels and launch gaps): the stage's
                algorithmic bytes and both kernels' flops over the measured
                time per stage, against the HBM and the ALU peaks;
-  cpu_baseline the CPU oracle (plain FP64, OpenMP) timed on one full RK step
-               of the same workload;
+  cpu_baseline the CPU oracle (plain FP64, OpenMP) timed on four full RK
+               steps of the same workload from its initial state;
   fp32_bulk    the same workload with FP32 bulk arithmetic (FP64 state/RK);
   turbulence_3d  the 3D driven-turbulence box, 128^3, p = 4 (FP64), with its
                own roofline record;
