@@ -440,6 +440,38 @@ def test_full_size_headline_step():
     assert state_err(w.cpu().numpy(), wr, 2, mom_scale=momentum_scale(ref, wr)) <= 1e-12
 
 
+def test_full_size_turbulence_steps_conserve():
+    """The 3D benchmark step at full size (128^3, p = 4, default tuned tiles),
+    a property that holds at any size: periodic faces cancel in the cell
+    means, so two dg_step_cfl steps keep the total mass to rounding with the
+    forcing on (it acts on momentum and energy only, Sec. 7) and every
+    conserved total with it off; the device dt equals the oracle's CFL step
+    of the initial state."""
+    order, n = 4, (128, 128, 128)
+    say("full size turbulence steps")
+    w0, s = W.turbulence(order, 128, device="cuda")
+    for forced in (True, False):
+        gpu, ref = pair(3, n, order, gamma=1.0001, nu=2e-5)
+        if forced:
+            gpu.set_forcing(s)
+        w = w0.clone()
+        t0 = np.array(gpu.totals(w))
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gpu.step_cfl(w, dt_dev)
+        if forced:
+            # CFL maxima over every Gauss point of the initial state, on the CPU
+            dtr = ref.max_dt(w0.cpu().numpy())[0]
+            assert abs(float(dt_dev) - dtr) <= 1e-14 * dtr
+        gpu.step_cfl(w, dt_dev)
+        assert gpu.check() == 0
+        t1 = np.array(gpu.totals(w))
+        scale = np.abs(t0) + np.abs(t0).max()
+        keep = [0] if forced else list(range(5))
+        assert np.all(np.abs(t1 - t0)[keep] <= 1e-13 * scale[keep]), (forced, t0, t1)
+        del gpu, w
+        torch.cuda.empty_cache()
+
+
 def test_fp32_bulk_density_wave_run():
     """Density wave, full run to t = 0.1 with FP32 bulk arithmetic against
     the FP64 oracle run: mean absolute density-coefficient error <= 1e-6."""
