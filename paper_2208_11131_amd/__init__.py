@@ -288,7 +288,9 @@ class Batch:
 
     def __del__(self):
         b = getattr(self, "b", None)
-        if b:
+        # at interpreter shutdown the module's globals may already be None:
+        # then the process is ending and the library's memory goes with it
+        if b and dg_batch_free is not None and lib is not None:
             dg_batch_free(b)
             self.b = None
 
@@ -352,7 +354,7 @@ class Solver:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
+        if ctx and dg_free is not None and lib is not None:   # see Batch.__del__
             dg_free(ctx)
             self.ctx = None
 
