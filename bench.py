@@ -6,29 +6,35 @@ viscous face flux; volume kernel: contractions, point fluxes, lift,
 projection and the FP64 stage combination).  The state is resident in HBM
 before the timed region; nothing leaves the device inside it.
 
-Default workload: the 2D Navier-Stokes Kelvin-Helmholtz shear layer,
-256 x 512 cells on [0,1]x[0,2], order p = 4 (16 modes x 4 fields per cell),
-nu = kappa = 1e-4, FP64.  Metric: DOF-updates per second per RK stage,
-(cells x modes x fields x stages) / time.
+Headline workload: the 3D driven-turbulence box, 128^3 cells on the periodic
+unit cube, order p = 4 (64 modes x 5 fields per cell, 671M DOFs), Navier-
+Stokes with nu = kappa = 2e-5 and the solenoidal driving source, gamma =
+1.0001, FP64 (the largest single-GPU configuration).  Metric: DOF-updates per
+second per RK stage, (cells x modes x fields x stages) / time; the median of
+five repeats of --steps timed steps after --warmup untimed ones.
 
 Extra objects on the JSON line:
-  roofline     dominant kernel (by device time): algorithmic bytes or flops per
-               launch over its average duration, measured with HIP events on
-               the launch stream around every kernel of the sampled steps of
-               the timed region (the last step and every 5th before it);
-  stage_roofline  the whole stage (all kernels and launch gaps): the stage's
+  roofline     dominant kernel (by device time): the stage's algorithmic bytes
+               (16 B/DOF at stage 1, 24 B/DOF after, the driving coefficients
+               once per stage) over its average duration, measured with HIP
+               events on the launch stream around every kernel of the sampled
+               steps of the timed region (the last step of each repeat and
+               every 5th before it);
+  stage_roofline  the whole stage (all kernels and launch gaps): the same
                algorithmic bytes and both kernels' flops over the measured
                time per stage, against the HBM and the ALU peaks;
-  cpu_baseline the CPU oracle (plain FP64, OpenMP) timed on four full RK
-               steps of the same workload from its initial state;
-  fp32_bulk    the same workload with FP32 bulk arithmetic (FP64 state/RK);
-  turbulence_3d  the 3D driven-turbulence box, 128^3, p = 4 (FP64), with its
-               own roofline record;
+  cpu_baseline the CPU oracle (plain FP64, OpenMP) on a fixed sample of cells
+               of the same state (RHS of the sampled cells), on one host core
+               and on all of them, scaled to DOF-updates per RK stage;
+  fp32_bulk    the same workload with FP32 bulk arithmetic (FP64 state/RK):
+               throughput, its RHS error against the oracle on sampled cells
+               and its state difference to the FP64 run after the same steps;
+  kh_2d        the 2D shear layer, 256 x 512, p = 4 (FP64 and FP32 bulk);
+  sod_av_2d    the AV shock tube, 1024 x 128, p = 6 (Euler + artificial
+               viscosity, outflow in x), FP64;
   ensemble     48 independent 2D boxes (sides 32..512, orders 2..6) stepped by
                one captured hipGraph (grouped launches for the small boxes),
                against the same steps issued box by box;
-  sod_av_2d    the AV shock tube, 1024 x 128, p = 6 (Euler + artificial
-               viscosity, outflow in x), FP64;
   kh_order_sweep  the shear layer at every order p = 2..8, FP64 and FP32 bulk
                (5 timed steps each), with the dominant kernel's roofline.
 """
@@ -105,17 +111,13 @@ def face_flops_per_cell(dim, p, F, Fc, grad, ns, av):
     return dim * (2 * mac + K * face_point_flops(dim, ns, av))
 
 
-def stage_arrays(stages):
-    """FP64 arrays touched by the volume kernel per stage (reads + writes):
-    stage 1 reads cur, writes out; later stages also read the base register;
-    the 4th stage of the 5-stage scheme reads one more and writes two."""
-    if stages == 1:
-        return [2]
-    if stages == 2:
-        return [2, 3]
-    if stages == 3:
-        return [2, 3, 3]
-    return [2, 3, 3, 5, 3]
+def stage_bytes_per_dof(stages):
+    """Algorithmic HBM bytes per DOF of each stage of an SSP-RK step (FP64
+    state): the first stage reads the state and writes the next register
+    (16 B), every later stage also reads the base register (24 B).  The
+    5-stage scheme's fourth stage also keeps a partial sum for the last one;
+    that register traffic depends on the storage scheme and is not counted."""
+    return [16.0] + [24.0] * (stages - 1)
 
 
 # ---------------------------------------------------------------------------
@@ -157,12 +159,7 @@ def group_err(a, b, dim):
     return e
 
 
-def run_steps(s, w, n):
-    for _ in range(n):
-        s.step_cfl(w)
-
-
-def measure(name, order, precision, steps, warmup, device="cuda"):
+def measure(name, order, precision, steps, warmup, repeats=1, device="cuda"):
     s, w, f, desc, phys = make_workload(name, order, device, precision)
     dim = phys["dim"]
     stages = 1 if order == 1 else 2 if order == 2 else 3 if order == 3 else 5
@@ -174,25 +171,30 @@ def measure(name, order, precision, steps, warmup, device="cuda"):
         s.step_cfl(w)
     dg.dg_timing_enable(s.ctx, False)
     torch.cuda.synchronize()
-    # timed region: K steps, events bracket it on the launch stream.  The
-    # per-kernel events (every launch of the sampled steps: the last step and
-    # every EVENT_EVERY-th before it) cost about 10 % of a step where they are
-    # recorded, so they are recorded on a sample of the steps only.
+    # timed region: `repeats` runs of `steps` steps, each bracketed by events
+    # on the launch stream.  The per-kernel events (every launch of the
+    # sampled steps: the last step and every EVENT_EVERY-th before it) cost
+    # about 10 % of a step where they are recorded, so they are recorded on a
+    # sample of the steps only.
     dg.dg_timing_read(s.ctx)
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for i in range(steps):
-        dg.dg_timing_enable(s.ctx, i in sampled)
-        s.step_cfl(w)
-    dg.dg_timing_enable(s.ctx, False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
+    runs = []
+    wall = 0.0
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for i in range(steps):
+            dg.dg_timing_enable(s.ctx, i in sampled)
+            s.step_cfl(w)
+        dg.dg_timing_enable(s.ctx, False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        runs.append(e0.elapsed_time(e1))
+    ms = float(np.median(runs))
     kt = dg.dg_timing_read(s.ctx)
     err = s.check()
     if err != 0:
@@ -205,10 +207,10 @@ def measure(name, order, precision, steps, warmup, device="cuda"):
     grad = phys["ns"] or phys["av"]
     vol_fl = vol_flops_per_cell(dim, p, F, Fc, grad, phys["ns"], phys["av"]) * s.ncells
     face_fl = face_flops_per_cell(dim, p, F, Fc, grad, phys["ns"], phys["av"]) * s.ncells
-    arrays = stage_arrays(stages)
-    vol_bytes = 8.0 * dofs * sum(arrays) / len(arrays)       # per launch (average over the stages)
+    bpd = stage_bytes_per_dof(stages)
+    vol_bytes = dofs * sum(bpd) / len(bpd)                   # per stage (average over the stages)
     if f is not None:
-        vol_bytes += 8.0 * s.ncells * dim * s.nmodes          # forcing coefficients
+        vol_bytes += 8.0 * s.ncells * dim * s.nmodes          # driving coefficients
     peak_tf = FP64_PEAK_TF if precision == "fp64" else FP32_PEAK_TF
     ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
     kern = {}
@@ -234,11 +236,21 @@ def measure(name, order, precision, steps, warmup, device="cuda"):
     stage = {"us": st_s * 1e6, "algorithmic_bytes": vol_bytes, "algorithmic_flops": vol_fl + face_fl,
              "achieved_gbs": vol_bytes / st_s / 1e9, "frac_hbm": vol_bytes / st_s / 1e9 / HBM_PEAK_GBS,
              "achieved_tflops": (vol_fl + face_fl) / st_s / 1e12,
-             "frac_alu": (vol_fl + face_fl) / st_s / 1e12 / peak_tf}
-    res = {"value": value, "stage": stage, "ms": ms, "wall_s": wall, "stages": stages, "dofs": dofs, "desc": desc, "steps": steps + warmup,
+             "frac_alu": (vol_fl + face_fl) / st_s / 1e12 / peak_tf,
+             "bytes_per_dof_by_stage": bpd}
+    res = {"value": value, "stage": stage, "ms": ms, "runs_ms": runs, "wall_s": wall, "stages": stages,
+           "dofs": dofs, "desc": desc, "steps": steps, "warmup": warmup, "repeats": repeats,
            "kernels": kern, "dominant": dom, "cfl_ms": kt["cfl"][0], "solver": s, "state": w,
-           "forcing": f}
+           "forcing": f, "phys": phys}
     return res
+
+
+def kernel_record(r):
+    d = r["kernels"][r["dominant"]]
+    return {"kernel": r["dominant"], "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+            "unit": d["unit"], "frac": d["frac"], "avg_us": d["avg_us"],
+            "other_kernels": {k: {kk: v[kk] for kk in ("bound", "achieved", "unit", "frac", "avg_us")}
+                              for k, v in r["kernels"].items() if k != r["dominant"]}}
 
 
 def measure_ensemble(steps, warmup):
@@ -298,42 +310,97 @@ def traffic_record(kernel, workload):
     return rec[key].get("bytes_per_launch")
 
 
-def cpu_baseline(desc, order, stages, dofs, nsteps=4):
-    """nsteps full RK steps of the CPU oracle from the workload's initial state
-    (about 10 s of CPU work on the host's cores)."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, order, one_core_cells=2048, all_core_cells=16384):
+    """The CPU oracle on a fixed sample of cells of the workload's initial
+    state: the RHS of every sampled cell (the whole state as input), timed on
+    one host core and on all of them; DOF-updates per RK stage = sampled DOFs
+    / time (the stage combination itself is a few flops per DOF, not timed)."""
     import oracle as O
-    if desc["workload"] != "kelvin_helmholtz_2d":
-        return None
-    nx, ny = desc["cells"]
-    w = W.kelvin_helmholtz(order, nx, ny, device="cpu").numpy()
-    prob = O.Problem(2, (nx, ny), 1.0 / nx, order, 5.0 / 3.0, nu=1e-4, kappa=1e-4)
-    el = 0.0
-    for _ in range(nsteps):
-        dt = prob.max_dt(w)[0]
+    if name == "turb":
+        wt, ft = W.turbulence(order, 128, device="cuda")
+        w = wt.cpu().numpy()
+        prob = O.Problem(3, (128, 128, 128), 1.0 / 128, order, 1.0001, nu=2e-5, kappa=2e-5)
+        prob.set_forcing(ft.cpu().numpy())
+        del wt, ft
+    elif name == "kh":
+        w = W.kelvin_helmholtz(order, 256, 512, device="cuda").cpu().numpy()
+        prob = O.Problem(2, (256, 512), 1.0 / 256, order, 5.0 / 3.0, nu=1e-4, kappa=1e-4)
+    else:
+        w = W.sod(order, 1024, 128, device="cuda").cpu().numpy()
+        prob = O.Problem(2, (1024, 128), 1.0 / 1024, order, 1.4, av={}, bc=(1, 0), cfl=0.3)
+    torch.cuda.empty_cache()
+    R = np.zeros(prob.ncells) if prob.av is not None else None
+    rng = np.random.default_rng(2208)
+    dof_cell = prob.nfields * prob.nmodes
+    out = {"unit": "DOF-updates/s per RK stage", "kind": "oracle", "cpu_model": _cpu_model(),
+           "nproc": os.cpu_count()}
+    all_threads = O.num_threads()
+    for key, ncell, nthr in (("one_core", one_core_cells, 1), ("all_cores", all_core_cells, all_threads)):
+        cells = np.sort(rng.choice(prob.ncells, size=min(ncell, prob.ncells), replace=False))
+        O.set_num_threads(nthr)
         t0 = time.perf_counter()
-        w, _ = prob.step(w, dt)
-        el += time.perf_counter() - t0
-    return {"value": dofs * stages * nsteps / el, "unit": "DOF-updates/s per RK stage", "cores": O.num_threads(),
-            "kind": "oracle", "seconds": el,
-            "sample": "%d full SSP-RK steps (%d stages each) of the %dx%d p=%d shear layer from its initial state"
-                      % (nsteps, stages, nx, ny, order)}
+        prob.rhs_cells(w, cells, R_prev=R)
+        el = time.perf_counter() - t0
+        out[key] = {"value": len(cells) * dof_cell / el, "cores": O.num_threads(), "seconds": el,
+                    "cells": int(len(cells))}
+    O.set_num_threads(all_threads)
+    out["value"] = out["all_cores"]["value"]
+    out["cores"] = out["all_cores"]["cores"]
+    out["sample"] = ("RHS of %d (one core) and %d (all cores) seeded random cells of the %s state, "
+                     "p = %d, as one RK stage each" % (out["one_core"]["cells"], out["all_cores"]["cells"],
+                                                         name, order))
+    return out
+
+
+def fp32_oracle_error(r32, ncell=24):
+    """RHS of the FP32-bulk path on the whole state against the oracle on
+    sampled cells, relative to the oracle's rounding scale and plainly."""
+    import oracle as O
+    from oracle.compare import rhs_err, rhs_plain
+    s, w, f = r32["solver"], r32["state"], r32["forcing"]
+    L = s.rhs(w).cpu().numpy()
+    wh = w.cpu().numpy()
+    d = r32["desc"]
+    if d["workload"] == "driven_turbulence_3d":
+        prob = O.Problem(3, tuple(d["cells"]), 1.0 / d["cells"][0], d["order"], 1.0001, nu=2e-5, kappa=2e-5)
+        prob.set_forcing(f.cpu().numpy())
+    elif d["workload"] == "kelvin_helmholtz_2d":
+        prob = O.Problem(2, tuple(d["cells"]), 1.0 / d["cells"][0], d["order"], 5.0 / 3.0, nu=1e-4, kappa=1e-4)
+    else:
+        return None
+    cells = np.sort(np.random.default_rng(7).choice(prob.ncells, size=ncell, replace=False))
+    Lr = prob.rhs_cells(wh, cells)
+    S = prob.rhs_abs(wh, cells=cells)
+    return {"rhs_err_vs_rounding_scale": rhs_err(L[cells], Lr, S, prob.dim),
+            "rhs_err_plain_per_group": rhs_plain(L[cells], Lr, prob.dim), "sampled_cells": ncell}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=60)
-    ap.add_argument("--config", default="kh", choices=["kh", "turb", "sod"])
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--repeats", type=int, default=5)
+    ap.add_argument("--config", default="turb", choices=["kh", "turb", "sod"])
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the fp32_bulk and turbulence_3d records")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline record")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes 3 times (counter calibration)")
     args = ap.parse_args()
-    if args.steps < 1 or args.warmup < 0:
-        print("bench.py needs --steps >= 1 and --warmup >= 0", file=sys.stderr)
+    if args.steps < 1 or args.warmup < 0 or args.repeats < 1:
+        print("bench.py needs --steps >= 1, --warmup >= 0 and --repeats >= 1", file=sys.stderr)
         sys.exit(2)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -352,14 +419,16 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n * 8}))
         return
-    print("bench: %s p=%d %s, %d warmup + %d timed steps" % (args.config, args.order, args.precision, args.warmup,
-                                                             args.steps), file=sys.stderr, flush=True)
-    res = measure(args.config, args.order, args.precision, args.steps, args.warmup)
+    print("bench: %s p=%d %s, %d warmup + %d x %d timed steps" % (args.config, args.order, args.precision,
+                                                                  args.warmup, args.repeats, args.steps),
+          file=sys.stderr, flush=True)
+    res = measure(args.config, args.order, args.precision, args.steps, args.warmup, args.repeats)
     dom = res["kernels"][res["dominant"]]
     kname = {"vol": "vol_kernel", "face": "face_kernel"}[res["dominant"]]
     roof = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"], "unit": dom["unit"],
             "frac": dom["frac"], "traffic": traffic_record(kname, res["desc"]["workload"]),
             "kernel": kname, "avg_us": dom["avg_us"], "launches": dom["launches"],
+            "algorithmic_bytes_per_launch": dom["algorithmic_bytes"],
             "other_kernels": {k: {kk: v[kk] for kk in ("bound", "achieved", "unit", "frac", "avg_us")}
                               for k, v in res["kernels"].items() if k != res["dominant"]}}
     line = {
@@ -368,73 +437,69 @@ def main():
         "ms_per_step": res["ms"] / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32-bulk/f64-state", "data": "synthetic",
         "config": dict(res["desc"], stages_per_step=res["stages"], dofs=res["dofs"],
-                       step="device CFL reduction + full SSP-RK step"),
+                       step="device CFL reduction + full SSP-RK step",
+                       timing="median of %d repeats of %d steps" % (args.repeats, args.steps),
+                       repeats_ms=res["runs_ms"]),
         "roofline": roof,
         "stage_roofline": res["stage"],
     }
-    desc, stages, dofs = res["desc"], res["stages"], res["dofs"]
+    name, order = args.config, args.order
     w64 = res["state"].cpu().numpy()
-    dim = 3 if desc["workload"].endswith("3d") else 2
+    dim = res["phys"]["dim"]
+    nsteps64 = args.warmup + args.steps * args.repeats
     del res
     torch.cuda.empty_cache()
     if not args.no_extras:
         print("bench: fp32 bulk", file=sys.stderr, flush=True)
-        n32 = args.steps + args.warmup - 2
-        r32 = measure(args.config, args.order, "fp32", n32, 2)
-        # error of the FP32-bulk state against the FP64 state after the same
-        # number of CFL steps from the same initial state
+        n32 = max(1, (nsteps64 - 2) // args.repeats)
+        r32 = measure(name, order, "fp32", n32, nsteps64 - n32 * args.repeats, args.repeats)
         err = group_err(r32["state"].cpu().numpy(), w64, dim)
-        line["fp32_bulk"] = {"value": r32["value"], "ms_per_step": r32["ms"] / n32,
-                             "speedup_vs_fp64": r32["value"] / line["value"],
-                             "state_err_vs_fp64": err, "after_steps": n32 + 2,
-                             "err_measure": "max over rho/momentum/energy of ||a-b||_inf/||b||_inf"}
+        rec = {"value": r32["value"], "ms_per_step": r32["ms"] / n32, "speedup_vs_fp64": r32["value"] / line["value"],
+               "state_err_vs_fp64_gpu": err, "after_steps": nsteps64,
+               "err_measure": "max over rho/momentum/energy of ||a-b||_inf/||b||_inf",
+               "roofline": kernel_record(r32), "stage_roofline": r32["stage"]}
+        print("bench: fp32 bulk vs oracle (sampled cells)", file=sys.stderr, flush=True)
+        rec["vs_oracle"] = fp32_oracle_error(r32)
+        line["fp32_bulk"] = rec
         del r32
         torch.cuda.empty_cache()
-        print("bench: 3D turbulence", file=sys.stderr, flush=True)
-        r3 = measure("turb", 4, "fp64", 5, 1)
-        d3 = r3["kernels"][r3["dominant"]]
-        line["turbulence_3d"] = {"value": r3["value"], "ms_per_step": r3["ms"] / 5, "config": r3["desc"],
-                                 "roofline": {"kernel": r3["dominant"], "bound": d3["bound"],
-                                              "achieved": d3["achieved"], "peak": d3["peak"], "unit": d3["unit"],
-                                              "frac": d3["frac"], "avg_us": d3["avg_us"],
-                                              "other_kernels": {k: {kk: v[kk] for kk in
-                                                                    ("bound", "achieved", "unit", "frac", "avg_us")}
-                                                                for k, v in r3["kernels"].items()
-                                                                if k != r3["dominant"]}},
-                                 "stage_roofline": r3["stage"]}
-        del r3
-        torch.cuda.empty_cache()
+        if name != "kh":
+            print("bench: 2D shear layer", file=sys.stderr, flush=True)
+            rk = measure("kh", 4, "fp64", 20, 60, 3)
+            rk32 = measure("kh", 4, "fp32", 20, 60, 3)
+            line["kh_2d"] = {"value": rk["value"], "ms_per_step": rk["ms"] / 20, "config": rk["desc"],
+                             "roofline": kernel_record(rk), "stage_roofline": rk["stage"],
+                             "fp32_bulk": {"value": rk32["value"], "speedup_vs_fp64": rk32["value"] / rk["value"],
+                                           "state_err_vs_fp64_gpu": group_err(rk32["state"].cpu().numpy(),
+                                                                              rk["state"].cpu().numpy(), 2)}}
+            del rk, rk32
+            torch.cuda.empty_cache()
         print("bench: shock tube (AV)", file=sys.stderr, flush=True)
-        rs = measure("sod", 6, "fp64", 5, 1)
-        ds = rs["kernels"][rs["dominant"]]
-        line["sod_av_2d"] = {"value": rs["value"], "ms_per_step": rs["ms"] / 5, "config": rs["desc"],
-                             "roofline": {"kernel": rs["dominant"], "bound": ds["bound"], "achieved": ds["achieved"],
-                                          "peak": ds["peak"], "unit": ds["unit"], "frac": ds["frac"],
-                                          "avg_us": ds["avg_us"]},
-                             "stage_roofline": rs["stage"]}
+        rs = measure("sod", 6, "fp64", 10, 5, 3)
+        line["sod_av_2d"] = {"value": rs["value"], "ms_per_step": rs["ms"] / 10, "config": rs["desc"],
+                             "roofline": kernel_record(rs), "stage_roofline": rs["stage"]}
         del rs
         torch.cuda.empty_cache()
         print("bench: ensemble", file=sys.stderr, flush=True)
         line["ensemble"] = measure_ensemble(5, 1)
         torch.cuda.empty_cache()
-        if args.config == "kh":
-            print("bench: order sweep", file=sys.stderr, flush=True)
-            sweep = {}
-            for p in range(2, 9):
-                rec = {}
-                for prec in ("fp64", "fp32"):
-                    r = measure("kh", p, prec, 5, 2)
-                    d = r["kernels"][r["dominant"]]
-                    rec[prec] = {"value": r["value"], "ms_per_step": r["ms"] / 5,
-                                 "dominant": r["dominant"], "bound": d["bound"], "frac": d["frac"],
-                                 "stage_frac_hbm": r["stage"]["frac_hbm"]}
-                    del r
-                    torch.cuda.empty_cache()
-                sweep[str(p)] = rec
-            line["kh_order_sweep"] = sweep
+        print("bench: order sweep", file=sys.stderr, flush=True)
+        sweep = {}
+        for p in range(2, 9):
+            rec = {}
+            for prec in ("fp64", "fp32"):
+                r = measure("kh", p, prec, 5, 2)
+                d = r["kernels"][r["dominant"]]
+                rec[prec] = {"value": r["value"], "ms_per_step": r["ms"] / 5,
+                             "dominant": r["dominant"], "bound": d["bound"], "frac": d["frac"],
+                             "stage_frac_hbm": r["stage"]["frac_hbm"]}
+                del r
+                torch.cuda.empty_cache()
+            sweep[str(p)] = rec
+        line["kh_order_sweep"] = sweep
     if not args.no_cpu_baseline:
-        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(desc, args.order, stages, dofs)
+        print("bench: cpu baseline (oracle, sampled cells)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(name, order)
     print(json.dumps(line), flush=True)
 
 

@@ -114,6 +114,12 @@ size_t dg_state_len(const dg_ctx *ctx);
 /* Number of fields per cell (dim + 2, + 1 with AV). */
 int dg_num_fields(const dg_ctx *ctx);
 
+/* Shape of the context (host pointers, any may be NULL): dimension, order p,
+ * number of cells and fields per cell.  A state array holds
+ * ncells * nfields * p^dim doubles, a forcing array (dg_set_forcing)
+ * ncells * dim * p^dim, a sensor-rate array ncells.  DG_EINVAL for NULL ctx. */
+dg_status dg_shape(const dg_ctx *ctx, int *dim, int *order, long long *ncells, int *nfields);
+
 /* wdot = dw/dt of the weight equations (Sec. 2.2 eq. weight_evolution,
  * discretised as Sec. 2.4 eq. time_stepping_final_analytical_equation, with
  * the viscous and AV fluxes of Sec. 3 and 4).  w and wdot must not overlap.
@@ -141,7 +147,11 @@ dg_status dg_max_dt(dg_ctx *ctx, const double *w, double *dt_out, double *cmax_o
                     void *stream);
 
 /* Conserved totals sum_K |K| w_0 per conserved field (dim + 2 values, host
- * pointer `out`), deterministic compensated FP64 sums.  Synchronises. */
+ * pointer `out`), deterministic compensated FP64 sums.  The integral of each
+ * conserved density over the box (Sec. 2.1: w_0 is the cell mean of the
+ * orthonormal expansion, so |K| w_0 is the cell's content); on periodic
+ * boxes the scheme keeps these constant (Sec. 3, manifestly conservative
+ * form with single-valued face fluxes).  Synchronises. */
 dg_status dg_conserved_totals(dg_ctx *ctx, const double *w, double *out, void *stream);
 
 /* Body-force acceleration field s (Sec. 7 driving): device array
@@ -204,6 +214,9 @@ dg_status dg_batch_step(dg_batch *b, double *const *w, int use_graph, void *stre
 /* Per-box step sizes of the last batched step (host array of nbox doubles).
  * Synchronises `stream`. */
 dg_status dg_batch_dt(dg_batch *b, double *dt_out, void *stream);
+
+/* Number of boxes of the batch (0 for NULL). */
+int dg_batch_size(const dg_batch *b);
 
 /* The context of box i (e.g. for per-box dg_step_cfl launches on the same
  * buffers, dg_rhs, totals).  Owned by the batch. */

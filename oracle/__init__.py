@@ -63,11 +63,13 @@ def _load():
             "or_sensor_rate": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, _D, _D]),
             "or_rhs": (None, [P, _D, _D, _D, _D]),
             "or_rhs_cells": (None, [P, _D, _D, ctypes.c_long, ctypes.POINTER(ctypes.c_long), _D]),
+            "or_rhs_abs": (None, [P, _D, _D, ctypes.c_long, ctypes.POINTER(ctypes.c_long), _D]),
             "or_max_dt": (ctypes.c_double, [P, _D, _D, _D]),
             "or_rk_stages": (ctypes.c_int, [ctypes.c_int]),
             "or_step": (None, [P, _D, ctypes.c_double, _D]),
             "or_totals": (None, [P, _D, _D]),
             "or_num_threads": (ctypes.c_int, []),
+            "or_set_num_threads": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -140,6 +142,23 @@ class Problem:
         Rp = None if R_prev is None else np.ascontiguousarray(R_prev, dtype=np.float64)
         lib.or_rhs_cells(ctypes.byref(self.p), _ptr(w), _ptr(Rp), len(cells),
                          cells.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _ptr(out))
+        return out
+
+    def rhs_abs(self, w, cells=None, R_prev=None):
+        """Rounding scale of the RHS: per coefficient, the sum of the
+        magnitudes of the summands of its volume, source and surface sums
+        (of the listed cells, or of every cell)."""
+        lib = _load()
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        Rp = None if R_prev is None else np.ascontiguousarray(R_prev, dtype=np.float64)
+        if cells is None:
+            out = np.zeros_like(w)
+            lib.or_rhs_abs(ctypes.byref(self.p), _ptr(w), _ptr(Rp), 0, None, _ptr(out))
+        else:
+            cells = np.ascontiguousarray(cells, dtype=np.int64)
+            out = np.zeros((len(cells), self.nfields, self.nmodes))
+            lib.or_rhs_abs(ctypes.byref(self.p), _ptr(w), _ptr(Rp), len(cells),
+                           cells.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _ptr(out))
         return out
 
     def step(self, w, dt, R_state=None):
@@ -230,3 +249,7 @@ def recovery_fraction(order):
 
 def num_threads():
     return _load().or_num_threads()
+
+
+def set_num_threads(n):
+    _load().or_set_num_threads(int(n))

@@ -562,7 +562,7 @@ double or_sensor_rate(int p, int d, const double *wrho, const double *wdrho)
  * (wiggle source, NULL = 0).  If R_out != NULL, R_out[c] receives the new
  * d ln S/dt of this state (Sec. 4.1). */
 static void rhs_cell(const or_params *pr, const double *w, const double *R_prev, long c, double *out,
-                     double *R_out_c)
+                     double *R_out_c, int absmode)
 {
     const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = d + 2;
     const int M = ipow(p, d), NP = M;
@@ -572,6 +572,8 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
     const int grad = need_grad(pr);
     double xg[OR_MAXP + 2], wg[OR_MAXP + 2];
     or_gauss(p, xg, wg);
+/* absmode: accumulate the magnitude of every summand instead of the summand */
+#define ABSM(x) (absmode ? fabs(x) : (x))
     {
         const double *wc = w + c * (long)F * M;
         for (int i = 0; i < F * M; ++i) out[i] = 0.0;
@@ -649,11 +651,11 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
                 for (int a = 0; a < d; ++a) {
                     double dphi = 1.0;
                     for (int b = 0; b < d; ++b) dphi *= (b == a) ? dPt[b][l[b]] : Pt[b][l[b]];
-                    for (int f = 0; f < Fc; ++f) out[f * M + m] += pref * gj * dphi * flux[a][f];
+                    for (int f = 0; f < Fc; ++f) out[f * M + m] += ABSM(pref * gj * dphi * flux[a][f]);
                 }
                 if (pr->forcing)
-                    for (int f = 0; f < Fc; ++f) out[f * M + m] += spref * gj * phi * fsrc[f];
-                if (pr->av_on) out[Fc * M + m] += spref * gj * phi * src_alpha;
+                    for (int f = 0; f < Fc; ++f) out[f * M + m] += ABSM(spref * gj * phi * fsrc[f]);
+                if (pr->av_on) out[Fc * M + m] += ABSM(spref * gj * phi * src_alpha);
             }
         }
 
@@ -691,7 +693,8 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
                         double phi = 1.0;
                         for (int b = 0; b < d; ++b) phi *= Pt[b][l[b]];
                         for (int f = 0; f < Fc; ++f)
-                            out[f * M + m] -= pref * (double)side * gk * phi * Fh[k * Fc + f];
+                            out[f * M + m] += absmode ? fabs(pref * gk * phi * Fh[k * Fc + f])
+                                                      : -pref * (double)side * gk * phi * Fh[k * Fc + f];
                     }
                 }
             }
@@ -701,9 +704,10 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
         /* d ln S/dt is kept only where S itself exceeds the onset threshold:
          * below it S is at rounding level and its log-rate is noise (the
          * wiggle trigger of Sec. 4.1 acts only above S_onset). */
-        if (R_out_c && pr->av_on)
+        if (R_out_c && pr->av_on && !absmode)
             *R_out_c = (S_cur > pr->s_onset / ((double)p * p)) ? or_sensor_rate(p, d, wc, out) : 0.0;
     }
+#undef ABSM
 }
 
 void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *wdot, double *R_out)
@@ -711,7 +715,7 @@ void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *
     const int M = ipow(pr->order, pr->dim), F = n_fields(pr);
     const long NC = n_cells(pr);
 #pragma omp parallel for schedule(dynamic, 4)
-    for (long c = 0; c < NC; ++c) rhs_cell(pr, w, R_prev, c, wdot + c * (long)F * M, R_out ? R_out + c : NULL);
+    for (long c = 0; c < NC; ++c) rhs_cell(pr, w, R_prev, c, wdot + c * (long)F * M, R_out ? R_out + c : NULL, 0);
 }
 
 /* RHS of the listed cells only (out[i] = dw/dt of cell cells[i]); w is the
@@ -721,7 +725,21 @@ void or_rhs_cells(const or_params *pr, const double *w, const double *R_prev, lo
 {
     const int M = ipow(pr->order, pr->dim), F = n_fields(pr);
 #pragma omp parallel for schedule(dynamic, 1)
-    for (long i = 0; i < ncells_sel; ++i) rhs_cell(pr, w, R_prev, cells[i], out + i * (long)F * M, NULL);
+    for (long i = 0; i < ncells_sel; ++i) rhs_cell(pr, w, R_prev, cells[i], out + i * (long)F * M, NULL, 0);
+}
+
+/* Rounding scale of the RHS of the listed cells (cells = NULL: every cell):
+ * for every coefficient, the sum of the magnitudes of the summands of its
+ * volume, source and surface sums (eq. time_stepping_final_analytical_equation).
+ * Two correct evaluations of the same sums in different orders differ by a
+ * small multiple of the unit roundoff times this scale. */
+void or_rhs_abs(const or_params *pr, const double *w, const double *R_prev, long ncells_sel, const long *cells,
+                double *out)
+{
+    const int M = ipow(pr->order, pr->dim), F = n_fields(pr);
+    const long n = cells ? ncells_sel : n_cells(pr);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < n; ++i) rhs_cell(pr, w, R_prev, cells ? cells[i] : i, out + i * (long)F * M, NULL, 1);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -847,6 +865,16 @@ void or_totals(const or_params *pr, const double *w, double *out)
         }
         out[f] = s + comp;
     }
+}
+
+/* Thread count of the OpenMP loops (<= 0: leave unchanged). */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int or_num_threads(void)

@@ -31,10 +31,13 @@ double or_sensor_rate(int p, int d, const double *wrho, const double *wdrho);
 void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *wdot, double *R_out);
 void or_rhs_cells(const or_params *pr, const double *w, const double *R_prev, long ncells_sel, const long *cells,
                   double *out);
+void or_rhs_abs(const or_params *pr, const double *w, const double *R_prev, long ncells_sel, const long *cells,
+                double *out);
 double or_max_dt(const or_params *pr, const double *w, double *cmax_out, double *vmax_out);
 int or_rk_stages(int order);
 void or_step(const or_params *pr, double *w, double dt, double *R_state);
 void or_totals(const or_params *pr, const double *w, double *out);
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 #endif

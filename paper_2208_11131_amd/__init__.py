@@ -55,6 +55,7 @@ _SIGS = {
     "dg_free": (None, [_V]),
     "dg_state_len": (ctypes.c_size_t, [_V]),
     "dg_num_fields": (ctypes.c_int, [_V]),
+    "dg_shape": (ctypes.c_int, [_V, _I, _I, ctypes.POINTER(ctypes.c_longlong), _I]),
     "dg_rhs": (ctypes.c_int, [_V, _V, _V, _V]),
     "dg_step": (ctypes.c_int, [_V, _V, ctypes.c_double, _V]),
     "dg_step_cfl": (ctypes.c_int, [_V, _V, _V, _V]),
@@ -76,6 +77,7 @@ _SIGS = {
     "dg_batch_step": (ctypes.c_int, [_V, ctypes.POINTER(_V), ctypes.c_int, _V]),
     "dg_batch_dt": (ctypes.c_int, [_V, _D, _V]),
     "dg_batch_box": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(_V)]),
+    "dg_batch_size": (ctypes.c_int, [_V]),
     "dg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
 }
 EXPORTS = tuple(_SIGS)
@@ -174,6 +176,14 @@ def dg_num_fields(ctx):
     return lib().dg_num_fields(ctx)
 
 
+def dg_shape(ctx):
+    """(dim, order, ncells, nfields) of a context."""
+    d, o, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    n = ctypes.c_longlong()
+    _chk(lib().dg_shape(ctx, ctypes.byref(d), ctypes.byref(o), ctypes.byref(n), ctypes.byref(f)), "dg_shape")
+    return d.value, o.value, n.value, f.value
+
+
 def dg_rhs(ctx, w, wdot, stream=None):
     n = dg_state_len(ctx)
     _chk(lib().dg_rhs(ctx, _dptr(w, n), _dptr(wdot, n), _stream(stream)), "dg_rhs")
@@ -203,15 +213,19 @@ def dg_conserved_totals(ctx, w, dim, stream=None):
 
 
 def dg_set_forcing(ctx, s):
-    _chk(lib().dg_set_forcing(ctx, None if s is None else _dptr(s)), "dg_set_forcing")
+    if s is None:
+        _chk(lib().dg_set_forcing(ctx, None), "dg_set_forcing")
+        return
+    dim, order, ncells, _ = dg_shape(ctx)
+    _chk(lib().dg_set_forcing(ctx, _dptr(s, ncells * dim * order ** dim)), "dg_set_forcing")
 
 
 def dg_set_sensor_rate(ctx, R, stream=None):
-    _chk(lib().dg_set_sensor_rate(ctx, _dptr(R), _stream(stream)), "dg_set_sensor_rate")
+    _chk(lib().dg_set_sensor_rate(ctx, _dptr(R, dg_shape(ctx)[2]), _stream(stream)), "dg_set_sensor_rate")
 
 
 def dg_get_sensor_rate(ctx, R, stream=None):
-    _chk(lib().dg_get_sensor_rate(ctx, _dptr(R), _stream(stream)), "dg_get_sensor_rate")
+    _chk(lib().dg_get_sensor_rate(ctx, _dptr(R, dg_shape(ctx)[2]), _stream(stream)), "dg_get_sensor_rate")
 
 
 def dg_check(ctx, stream=None):
@@ -253,8 +267,15 @@ def dg_batch_free(b):
     lib().dg_batch_free(b)
 
 
+def dg_batch_size(b):
+    return lib().dg_batch_size(b)
+
+
 def dg_batch_step(b, ws, use_graph=True, stream=None):
-    ptrs = (_V * len(ws))(*[_dptr(w) for w in ws])
+    nbox = dg_batch_size(b)
+    if len(ws) != nbox:
+        raise ValueError("dg_batch_step: %d state tensors for %d boxes" % (len(ws), nbox))
+    ptrs = (_V * nbox)(*[_dptr(w, dg_state_len(dg_batch_box(b, i))) for i, w in enumerate(ws)])
     _chk(lib().dg_batch_step(b, ptrs, 1 if use_graph else 0, _stream(stream)), "dg_batch_step")
 
 

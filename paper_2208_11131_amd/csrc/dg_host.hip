@@ -925,6 +925,16 @@ size_t dg_state_len(const dg_ctx *c) { return c ? (size_t)c->ncells * c->F * c->
 
 int dg_num_fields(const dg_ctx *c) { return c ? c->F : 0; }
 
+dg_status dg_shape(const dg_ctx *c, int *dim, int *order, long long *ncells, int *nfields)
+{
+    if (!c) return DG_EINVAL;
+    if (dim) *dim = c->dim;
+    if (order) *order = c->P;
+    if (ncells) *ncells = c->ncells;
+    if (nfields) *nfields = c->F;
+    return DG_OK;
+}
+
 // The kernels move the state in 16-byte groups.
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
@@ -1197,12 +1207,16 @@ static dg_status batch_init_impl(int nbox, const dg_mesh *meshes, const int *ord
         if (meshes[i].dim != meshes[0].dim) return DG_EINVAL;
     dg_batch *b = new (std::nothrow) dg_batch;
     if (!b) return DG_ENOMEM;
-    // releases the partly built batch on every early return (and exception)
+    // releases the partly built batch (every box context initialised so far
+    // and every group table allocated so far) on each early return and on an
+    // exception; disarmed once the batch is complete
     struct Guard {
         dg_batch *b;
         ~Guard()
         {
             if (b) {
+                batch_release(b);
+                delete b;
             }
         }
     } guard{b};
@@ -1279,10 +1293,14 @@ static dg_status batch_init_impl(int nbox, const dg_mesh *meshes, const int *ord
             }
             g.h_desc.push_back(d);
         }
-        if (!ok(hipMalloc(&g.d_desc, sizeof(dgk::BoxDesc) * g.h_desc.size()))) {
+        // owned by the batch before the allocation, so that the guard frees it
+        b->groups.push_back(g);
+        Group &gb = b->groups.back();
+        if (!ok(hipMalloc(&gb.d_desc, sizeof(dgk::BoxDesc) * gb.h_desc.size()))) {
+            gb.d_desc = nullptr;
+            (void)hipGetLastError();
             return DG_ENOMEM;
         }
-        b->groups.push_back(g);
     }
     guard.b = nullptr;
     *out = b;
@@ -1367,6 +1385,8 @@ dg_status dg_batch_dt(dg_batch *b, double *dt_out, void *stream)
             return DG_EDEVICE;
     return ok(hipStreamSynchronize(s)) ? DG_OK : DG_EDEVICE;
 }
+
+int dg_batch_size(const dg_batch *b) { return b ? b->nbox : 0; }
 
 dg_status dg_batch_box(dg_batch *b, int i, dg_ctx **ctx)
 {

@@ -113,3 +113,45 @@ def test_batch_rejects_av_and_mixed_dims():
     av = dg.dg_av_defaults()
     with pytest.raises(dg.DgError):
         dg.dg_batch_init([m2], [2], 1.4, av=av)
+
+
+def test_batch_init_failure_releases_everything():
+    """dg_batch_init with a valid first box and an invalid later order fails
+    with DG_EINVAL and frees the boxes it had already set up (device memory
+    returns to its starting level over repeated attempts)."""
+    say("batch init failure leak")
+    meshes = [dg.make_mesh(2, (256, 256)), dg.make_mesh(2, (32, 32))]
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(12):
+        with pytest.raises(dg.DgError) as ei:
+            dg.dg_batch_init(meshes, [4, 9], 5.0 / 3.0)
+        assert ei.value.code == dg.DG_EINVAL
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    # one 256^2 p = 4 box holds about 25 MB of registers: twelve leaks would be ~300 MB
+    assert free0 - free1 < 32 * 2 ** 20, (free0, free1)
+
+
+def test_binding_rejects_wrong_lengths_before_launch():
+    """Short or long tensors never reach the library: the binding checks the
+    element counts of the batch's state list, the forcing field and the
+    sensor-rate arrays and raises ValueError."""
+    say("binding length checks")
+    bt = dg.Batch(2, [16, 32], [2, 3], 5.0 / 3.0)
+    ws = [torch.ones(16 * 16 * 4 * 4, dtype=torch.float64, device="cuda"),
+          torch.ones(32 * 32 * 4 * 9, dtype=torch.float64, device="cuda")]
+    with pytest.raises(ValueError):
+        bt.step(ws[:1])
+    with pytest.raises(ValueError):
+        bt.step([ws[0], ws[1][:-4]])
+    s3 = dg.Solver(3, (3, 3, 2), 2, 1.4, nu=1e-3, kappa=1e-3)
+    with pytest.raises(ValueError):
+        s3.set_forcing(torch.zeros(18 * 3 * 8 - 1, dtype=torch.float64, device="cuda"))
+    s3.set_forcing(torch.zeros(18 * 3 * 8, dtype=torch.float64, device="cuda"))
+    s2 = dg.Solver(2, (5, 4), 3, 1.4, av={})
+    with pytest.raises(ValueError):
+        s2.set_sensor_rate(torch.zeros(19, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        dg.dg_get_sensor_rate(s2.ctx, torch.zeros(21, dtype=torch.float64, device="cuda"))
+    assert dg.dg_shape(s2.ctx) == (2, 3, 20, 5)

@@ -2,9 +2,11 @@
 
 Bars (stated per test; error measures in oracle/compare.py, per field group
 rho / momentum vector / energy / alpha):
-  * FP64 path: 1e-12 for dg_rhs (relative to max(||L||, rate ||w||), rate =
-    2p(c+|v|)/h) and for 1 and 10 dg_step's (relative to ||w||); 1e-14 for
-    dg_max_dt and the totals;
+  * FP64 path: dg_rhs within 1e-12 of the oracle's rounding scale S of the
+    same sums (per group ||L - Lr||_inf / ||S||_inf; the plain
+    ||L - Lr||_inf / ||Lr||_inf is printed next to it); 1 and 10 dg_step's
+    within 1e-12 relative to ||w|| (the increments' own relative error is
+    printed and bounded by 1e-9); 1e-14 for dg_max_dt and the totals;
   * FP32-bulk path: the bound is stated in the test (measured, see the design
     notes).
 Inputs come from the seeded generators of paper_2208_11131_amd.workloads; the
@@ -18,7 +20,7 @@ import pytest
 import torch
 
 import oracle as O
-from oracle.compare import cfl_rate, momentum_scale, rhs_err, state_err
+from oracle.compare import incr_err, momentum_scale, rhs_err, rhs_plain, state_err
 from paper_2208_11131_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -53,9 +55,21 @@ def relerr(a, b, ref):
     return state_err(a, b, ref.dim, mom_scale=momentum_scale(ref, b))
 
 
-def rerr(L, Lr, w, ref):
-    """RHS error relative to max(||L_g||, rate ||w_g||), rate = 2p(c+|v|)/h."""
-    return rhs_err(L, Lr, w, ref.dim, cfl_rate(ref, w), mom_scale=momentum_scale(ref, w))
+def rerr(L, Lr, w, ref, R_prev=None, cells=None):
+    """RHS error relative to the oracle's rounding scale of the same sums
+    (prints the plain per-group relative error too)."""
+    S = ref.rhs_abs(w, cells=cells, R_prev=R_prev)
+    e = rhs_err(L, Lr, S, ref.dim)
+    say("  rhs err / rounding scale %.2e, plain per group %s" % (e, ["%.1e" % x for x in rhs_plain(L, Lr, ref.dim)]))
+    return e
+
+
+def step_ok(wg, wr, w0, ref, tol=1e-12, itol=1e-9):
+    """State within tol of ||w|| per group; the increments within itol."""
+    e = relerr(wg, wr, ref)
+    ie = incr_err(wg, wr, w0, ref.dim)
+    say("  state err %.2e, increment err %.2e" % (e, ie))
+    return e <= tol and ie <= itol
 
 
 def state(dim, n, order, prob, seed, vbase=(0, 0, 0)):
@@ -80,7 +94,7 @@ def test_rhs_parity_2d(order, phys, bc):
         gpu.set_sensor_rate(torch.tensor(R, device="cuda"))
     L = gpu.rhs(torch.tensor(w0, device="cuda")).cpu().numpy()
     Lr = ref.rhs(w0, R_prev=R)
-    assert rerr(L, Lr, w0, ref) <= 1e-12
+    assert rerr(L, Lr, w0, ref, R_prev=R) <= 1e-12
 
 
 @pytest.mark.parametrize("order,phys,bc", RHS_3D)
@@ -90,8 +104,9 @@ def test_rhs_parity_3d(order, phys, bc):
     gpu, ref = pair(3, n, order, bc=bc, **PHYS[phys])
     w0 = state(3, n, order, ref, seed=10 + order)
     L = gpu.rhs(torch.tensor(w0, device="cuda")).cpu().numpy()
-    Lr = ref.rhs(w0, R_prev=np.zeros(ref.ncells) if ref.av is not None else None)
-    assert rerr(L, Lr, w0, ref) <= 1e-12
+    Rz = np.zeros(ref.ncells) if ref.av is not None else None
+    Lr = ref.rhs(w0, R_prev=Rz)
+    assert rerr(L, Lr, w0, ref, R_prev=Rz) <= 1e-12
 
 
 @pytest.mark.parametrize("order", [7, 8])
@@ -112,8 +127,9 @@ def test_rhs_fp32_bulk(dim, order, phys):
     gpu, ref = pair(dim, n, order, precision="fp32", **PHYS[phys])
     w0 = state(dim, n, order, ref, seed=30 + order)
     L = gpu.rhs(torch.tensor(w0, device="cuda")).cpu().numpy()
-    Lr = ref.rhs(w0, R_prev=np.zeros(ref.ncells) if ref.av is not None else None)
-    assert rerr(L, Lr, w0, ref) <= 2e-5
+    Rz = np.zeros(ref.ncells) if ref.av is not None else None
+    Lr = ref.rhs(w0, R_prev=Rz)
+    assert rerr(L, Lr, w0, ref, R_prev=Rz) <= 1e-5
 
 
 @pytest.mark.parametrize("dim,order,phys,nsteps", [(2, 1, "euler", 10), (2, 2, "nsav", 10), (2, 3, "ns", 10),
@@ -130,10 +146,13 @@ def test_step_parity(dim, order, phys, nsteps):
     for _ in range(nsteps):
         gpu.step(w, dt)
         wr, Rr = ref.step(wr, dt, Rr)
-    assert relerr(w.cpu().numpy(), wr, ref) <= 1e-12
+    assert step_ok(w.cpu().numpy(), wr, w0, ref)
     assert gpu.check() == 0
     if ref.av is not None:
-        np.testing.assert_allclose(gpu.get_sensor_rate().cpu().numpy(), Rr, rtol=1e-9, atol=1e-9)
+        Rg = gpu.get_sensor_rate().cpu().numpy()
+        eR = np.abs(Rg - Rr).max() / max(np.abs(Rr).max(), 1e-300)
+        say("  sensor-rate err %.2e (of max |R| = %.2e)" % (eR, np.abs(Rr).max()))
+        assert eR <= 1e-10
 
 
 @pytest.mark.parametrize("dim,order", [(2, 1), (2, 5), (3, 3)])
@@ -178,7 +197,7 @@ def test_step_cfl_uses_device_dt():
     dtr = ref.max_dt(w0)[0]
     assert abs(dt_dev.item() - dtr) <= 1e-14 * dtr
     wr, _ = ref.step(w0, dt_dev.item())
-    assert relerr(w.cpu().numpy(), wr, ref) <= 1e-12
+    assert step_ok(w.cpu().numpy(), wr, w0, ref)
 
 
 def test_density_wave_full_run():
@@ -220,7 +239,7 @@ def test_kelvin_helmholtz_reduced(order):
     dt = ref.max_dt(w0)[0]
     gpu.step(w, dt)
     wr, _ = ref.step(w0, dt)
-    assert relerr(w.cpu().numpy(), wr, ref) <= 1e-12
+    assert step_ok(w.cpu().numpy(), wr, w0, ref)
 
 
 def test_sod_reduced_and_y_uniform():
@@ -261,7 +280,7 @@ def test_turbulence_reduced_with_forcing():
     dt = ref.max_dt(w0)[0]
     gpu.step(w, dt)
     wr, _ = ref.step(w0, dt)
-    assert relerr(w.cpu().numpy(), wr, ref) <= 1e-12
+    assert step_ok(w.cpu().numpy(), wr, w0, ref)
 
 
 def test_ensemble_boxes_reduced():
@@ -350,7 +369,8 @@ def test_degenerate_meshes(n):
     gpu, ref = pair(2, n, order, bc=(1, 1), **PHYS["nsav"])
     w0 = state(2, n, order, ref, seed=90)
     L = gpu.rhs(torch.tensor(w0, device="cuda")).cpu().numpy()
-    assert rerr(L, ref.rhs(w0, R_prev=np.zeros(ref.ncells)), w0, ref) <= 1e-12
+    Rz = np.zeros(ref.ncells)
+    assert rerr(L, ref.rhs(w0, R_prev=Rz), w0, ref, R_prev=Rz) <= 1e-12
 
 
 def test_error_flags():
@@ -417,8 +437,9 @@ def test_full_size_sampled(cfg):
     L = gpu.rhs(w).cpu().numpy()
     wh = w.cpu().numpy()
     cells = _sampled_cells(ref.ncells, 24, rng)
-    Lr = ref.rhs_cells(wh, cells, R_prev=np.zeros(ref.ncells) if ref.av is not None else None)
-    assert rhs_err(L[cells], Lr, wh, ref.dim, cfl_rate(ref, wh), mom_scale=momentum_scale(ref, wh)) <= 1e-12
+    Rz = np.zeros(ref.ncells) if ref.av is not None else None
+    Lr = ref.rhs_cells(wh, cells, R_prev=Rz)
+    assert rerr(L[cells], Lr, wh, ref, R_prev=Rz, cells=cells) <= 1e-12
 
 
 def test_full_size_headline_step():
@@ -437,7 +458,7 @@ def test_full_size_headline_step():
     dtr = ref.max_dt(w0)[0]
     assert abs(float(dt_dev) - dtr) <= 1e-14 * dtr
     wr, _ = ref.step(w0, float(dt_dev))
-    assert state_err(w.cpu().numpy(), wr, 2, mom_scale=momentum_scale(ref, wr)) <= 1e-12
+    assert step_ok(w.cpu().numpy(), wr, w0, ref)
 
 
 def test_full_size_turbulence_steps_conserve():
