@@ -31,7 +31,7 @@ Extra objects on the JSON line:
                and its state difference to the FP64 run after the same steps;
   kh_2d        the 2D shear layer, 256 x 512, p = 4 (FP64 and FP32 bulk);
   sod_av_2d    the AV shock tube, 1024 x 128, p = 6 (Euler + artificial
-               viscosity, outflow in x), FP64;
+               viscosity, reflecting walls at the x ends), FP64;
   ensemble     48 independent 2D boxes (sides 32..512, orders 2..6) stepped by
                one captured hipGraph (grouped launches for the small boxes),
                against the same steps issued box by box;
@@ -142,7 +142,7 @@ def make_workload(name, order, device, precision):
     if name == "sod":
         nx, ny = 1024, 128
         w = W.sod(order, nx, ny, device=device)
-        s = dg.Solver(2, (nx, ny), order, 1.4, hi=[1.0, ny / nx], bc=[1, 0], av={}, precision=precision,
+        s = dg.Solver(2, (nx, ny), order, 1.4, hi=[1.0, ny / nx], bc=[2, 0], av={}, precision=precision,
                       cfl=0.3)
         desc = {"workload": "sod_av_2d", "cells": [nx, ny], "order": order, "fields": 5,
                 "physics": "euler + artificial viscosity", "gamma": 1.4}
@@ -337,7 +337,7 @@ def cpu_baseline(name, order, one_core_cells=2048, all_core_cells=16384):
         prob = O.Problem(2, (256, 512), 1.0 / 256, order, 5.0 / 3.0, nu=1e-4, kappa=1e-4)
     else:
         w = W.sod(order, 1024, 128, device="cuda").cpu().numpy()
-        prob = O.Problem(2, (1024, 128), 1.0 / 1024, order, 1.4, av={}, bc=(1, 0), cfl=0.3)
+        prob = O.Problem(2, (1024, 128), 1.0 / 1024, order, 1.4, av={}, bc=(2, 0), cfl=0.3)
     torch.cuda.empty_cache()
     R = np.zeros(prob.ncells) if prob.av is not None else None
     rng = np.random.default_rng(2208)

@@ -48,12 +48,21 @@ typedef enum {
     DG_EUNSUPPORTED = -6    /* valid request this build does not implement */
 } dg_status;
 
-typedef enum { DG_BC_PERIODIC = 0, DG_BC_OUTFLOW = 1 } dg_bc;
+typedef enum { DG_BC_PERIODIC = 0, DG_BC_OUTFLOW = 1, DG_BC_WALL = 2 } dg_bc;
 
 /* Mesh: dim in {2,3}; n[a] cells on [lo[a], hi[a]] along axis a (entries of
  * unused axes ignored).  Cells must be cubic: (hi-lo)/n equal on every axis
- * to 1e-12 relative (Sec. 2.1).  DG_BC_OUTFLOW uses a mirrored ghost cell,
- * w_ghost(l_a) = (-1)^{l_a} w(l_a), on both ends of that axis. */
+ * to 1e-12 relative (Sec. 2.1).  Non-periodic ends (the paper's problems are
+ * periodic; these are this library's boundary readings) use a ghost cell
+ * built from the boundary cell itself, on both ends of that axis:
+ *   DG_BC_OUTFLOW  mirrored ghost w_ghost(l_a) = (-1)^{l_a} w(l_a)
+ *                  (transmissive: the face states are equal).  At high
+ *                  order it is not stable over many steps: a rounding-level
+ *                  disturbance grows at the boundary (measured at p = 6 by
+ *                  about 0.4 % per step);
+ *   DG_BC_WALL     reflecting wall: the mirrored ghost with the momentum
+ *                  component normal to the boundary negated (no mass flux
+ *                  through the boundary; stable). */
 typedef struct {
     int dim;
     int n[3];

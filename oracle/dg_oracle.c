@@ -164,8 +164,10 @@ static void mode_degrees(int p, int dim, int m, int *l)
 }
 
 /* Coefficients of the neighbour of cell c across its side (dir a, side s = -1
- * lower, +1 upper).  Periodic boundaries wrap; outflow boundaries use the
- * mirror image of the cell itself, w_ghost(l_a) = (-1)^{l_a} w(l_a). */
+ * lower, +1 upper).  Periodic boundaries wrap; outflow boundaries (bc 1) use
+ * the mirror image of the cell itself, w_ghost(l_a) = (-1)^{l_a} w(l_a);
+ * reflecting walls (bc 2) use the same mirror image with the momentum
+ * component normal to the wall negated. */
 static void neighbour_coeffs(const or_params *pr, const double *w, long c, int a, int s, double *out)
 {
     const int p = pr->order, d = pr->dim, F = n_fields(pr), M = ipow(p, d);
@@ -187,7 +189,9 @@ static void neighbour_coeffs(const or_params *pr, const double *w, long c, int a
         for (int m = 0; m < M; ++m) {
             int l[3];
             mode_degrees(p, d, m, l);
-            out[f * M + m] = (l[a] & 1) ? -own[f * M + m] : own[f * M + m];
+            double sgn = (l[a] & 1) ? -1.0 : 1.0;
+            if (pr->bc[a] == 2 && f == 1 + a) sgn = -sgn;
+            out[f * M + m] = sgn * own[f * M + m];
         }
 }
 
@@ -457,10 +461,56 @@ void or_recover_face(const or_params *pr, const double *wL, const double *wR, in
 /* Face flux                                                                  */
 /* ------------------------------------------------------------------------- */
 
+/* Magnitude of the terms of the HLLC flux of or_hllc, per component:
+ * F = F_K + S_K (U*_K - U_K) on either side K, so the rounding of F is bounded
+ * by a multiple of |F_L| + |F_R| + |S_L| (|U*_L| + |U_L|) + |S_R| (|U*_R| + |U_R|)
+ * (both sides: the branch may flip where S* crosses 0). */
+static void hllc_terms_abs(int d, double gamma, const double *uL, const double *uR, int a, double *A)
+{
+    const int Fc = d + 2;
+    double fL[5], fR[5];
+    or_euler_flux(d, gamma, uL, a, fL);
+    or_euler_flux(d, gamma, uR, a, fR);
+    const double *u2[2] = {uL, uR};
+    double S[2], us[2][5];
+    double rL = uL[0], rR = uR[0], vL2 = 0, vR2 = 0;
+    for (int i = 0; i < d; ++i) {
+        vL2 += (uL[1 + i] / rL) * (uL[1 + i] / rL);
+        vR2 += (uR[1 + i] / rR) * (uR[1 + i] / rR);
+    }
+    double pL = (gamma - 1.0) * (uL[d + 1] - 0.5 * rL * vL2);
+    double pR = (gamma - 1.0) * (uR[d + 1] - 0.5 * rR * vR2);
+    double cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+    double unL = uL[1 + a] / rL, unR = uR[1 + a] / rR;
+    S[0] = fmin(unL - cL, unR - cR);
+    S[1] = fmax(unL + cL, unR + cR);
+    double Ss = (pR - pL + rL * unL * (S[0] - unL) - rR * unR * (S[1] - unR)) /
+                (rL * (S[0] - unL) - rR * (S[1] - unR));
+    for (int sd = 0; sd < 2; ++sd) {
+        const double *u = u2[sd];
+        double r = u[0], un = u[1 + a] / r, pK = sd == 0 ? pL : pR;
+        double fac = r * (S[sd] - un) / (S[sd] - Ss);
+        us[sd][0] = fac;
+        for (int i = 0; i < d; ++i) us[sd][1 + i] = (i == a) ? fac * Ss : fac * (u[1 + i] / r);
+        us[sd][d + 1] = fac * (u[d + 1] / r + (Ss - un) * (Ss + pK / (r * (S[sd] - un))));
+    }
+    for (int k = 0; k < Fc; ++k)
+        A[k] = fabs(fL[k]) + fabs(fR[k]) + fabs(S[0]) * (fabs(us[0][k]) + fabs(uL[k])) +
+               fabs(S[1]) * (fabs(us[1][k]) + fabs(uR[k]));
+}
+
 /* Single-valued face flux Fh[k*Fc + f] at the p^{d-1} face points of the face
  * between wL (lower) and wR (upper) along a: HLLC on the raw traces minus the
- * viscous (Navier-Stokes + AV) flux on the recovered state. */
+ * viscous (Navier-Stokes + AV) flux on the recovered state.  absmode: the
+ * magnitudes of the terms of that flux instead (rounding scale). */
+static void face_flux_m(const or_params *pr, const double *wL, const double *wR, int a, double *Fh, int absmode);
+
 static void face_flux(const or_params *pr, const double *wL, const double *wR, int a, double *Fh)
+{
+    face_flux_m(pr, wL, wR, a, Fh, 0);
+}
+
+static void face_flux_m(const or_params *pr, const double *wL, const double *wR, int a, double *Fh, int absmode)
 {
     const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = d + 2;
     double xg[OR_MAXP + 2], wg[OR_MAXP + 2];
@@ -487,18 +537,22 @@ static void face_flux(const or_params *pr, const double *wL, const double *wR, i
         eval_state(p, d, F, wL, xi, uL, NULL);
         xi[a] = -1.0;
         eval_state(p, d, F, wR, xi, uR, NULL);
-        or_hllc(d, pr->gamma, uL, uR, a, Fh + k * Fc);
+        if (absmode)
+            hllc_terms_abs(d, pr->gamma, uL, uR, a, Fh + k * Fc);
+        else
+            or_hllc(d, pr->gamma, uL, uR, a, Fh + k * Fc);
         if (need_grad(pr)) {
             const double *u = ut + k * F;
             const double *g = gt + k * d * F;
             if (pr->nu > 0.0 || pr->kappa > 0.0) {
                 double fv[5];
                 ns_flux(d, pr->gamma, pr->nu, pr->kappa, u, g, F, a, fv);
-                for (int f = 0; f < Fc; ++f) Fh[k * Fc + f] -= fv[f];
+                for (int f = 0; f < Fc; ++f) Fh[k * Fc + f] += absmode ? fabs(fv[f]) : -fv[f];
             }
             if (pr->av_on) {
                 double eps = av_eps(pr, u[Fc], sound_speed(d, pr->gamma, u));
-                for (int f = 0; f < Fc; ++f) Fh[k * Fc + f] -= eps * g[a * F + f];
+                for (int f = 0; f < Fc; ++f)
+                    Fh[k * Fc + f] += absmode ? fabs(eps * g[a * F + f]) : -eps * g[a * F + f];
             }
         }
     }
@@ -673,9 +727,9 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
             for (int side = -1; side <= 1; side += 2) {
                 neighbour_coeffs(pr, w, c, a, side, nb);
                 if (side < 0)
-                    face_flux(pr, nb, wc, a, Fh);
+                    face_flux_m(pr, nb, wc, a, Fh, absmode);
                 else
-                    face_flux(pr, wc, nb, a, Fh);
+                    face_flux_m(pr, wc, nb, a, Fh, absmode);
                 for (int k = 0; k < K; ++k) {
                     double xi[3], gk = 1.0;
                     int kk = k;
@@ -730,9 +784,11 @@ void or_rhs_cells(const or_params *pr, const double *w, const double *R_prev, lo
 
 /* Rounding scale of the RHS of the listed cells (cells = NULL: every cell):
  * for every coefficient, the sum of the magnitudes of the summands of its
- * volume, source and surface sums (eq. time_stepping_final_analytical_equation).
- * Two correct evaluations of the same sums in different orders differ by a
- * small multiple of the unit roundoff times this scale. */
+ * volume, source and surface sums (eq. time_stepping_final_analytical_equation),
+ * each surface summand taken with the magnitudes of the terms of its face
+ * flux (HLLC: F_K and S_K (U*_K - U_K) on both sides; the viscous and AV
+ * parts).  Two correct evaluations of the same sums in different orders
+ * differ by a small multiple of the unit roundoff times this scale. */
 void or_rhs_abs(const or_params *pr, const double *w, const double *R_prev, long ncells_sel, const long *cells,
                 double *out)
 {

@@ -10,7 +10,7 @@
 typedef struct {
     int dim;           /* 2 or 3 */
     int n[3];          /* cells per axis */
-    int bc[3];         /* 0 periodic, 1 outflow (mirrored ghost) */
+    int bc[3];         /* 0 periodic, 1 outflow (mirrored ghost), 2 reflecting wall */
     double h;          /* cubic cell size */
     int order;         /* p = n + 1 modes and Gauss points per axis */
     double gamma, nu, kappa;

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgmi.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_ENONPHYSICAL, DG_ENONFINITE, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-DG_BC_PERIODIC, DG_BC_OUTFLOW = 0, 1
+DG_BC_PERIODIC, DG_BC_OUTFLOW, DG_BC_WALL = 0, 1, 2
 DG_PREC_FP64, DG_PREC_FP32_BULK = 0, 1
 
 

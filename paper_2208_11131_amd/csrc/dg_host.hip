@@ -677,7 +677,8 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         if (mesh->n[a] < 1 || !(mesh->hi[a] > mesh->lo[a])) return DG_EINVAL;
         cells *= (long long)mesh->n[a] + 1;     // bounds the face counts too
         if (cells > kMaxIndex) return DG_EINVAL;
-        if (mesh->bc[a] != DG_BC_PERIODIC && mesh->bc[a] != DG_BC_OUTFLOW) return DG_EINVAL;
+        if (mesh->bc[a] != DG_BC_PERIODIC && mesh->bc[a] != DG_BC_OUTFLOW && mesh->bc[a] != DG_BC_WALL)
+            return DG_EINVAL;
         const double ha = (mesh->hi[a] - mesh->lo[a]) / mesh->n[a];
         if (a == 0)
             h = ha;
@@ -714,7 +715,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     for (int a = 0; a < 3; ++a) {
         g.n[a] = a < d ? mesh->n[a] : 1;
         g.bc[a] = a < d ? mesh->bc[a] : 0;
-        g.nf[a] = g.n[a] + (g.bc[a] == DG_BC_OUTFLOW ? 1 : 0);
+        g.nf[a] = g.n[a] + (g.bc[a] != DG_BC_PERIODIC ? 1 : 0);
         c->ncells *= g.n[a];
     }
     g.ncells = c->ncells;

@@ -449,6 +449,9 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     T *Sx = (T *)(smem + (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16);   // [5][C][F][NAF]
     T *A = Sx + 5 * Q;                                    // [NA][C][F][NAF]
 
+    // ghost slots of non-periodic ends: mir = 1 mirrored ghost (odd normal
+    // modes negated), 2 reflecting wall (the same, and the normal momentum
+    // negated as a whole)
     for (int s = tid; s <= C; s += nt) {
         int ca = a0 + s - 1;
         int m = 0;
@@ -457,10 +460,10 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         } else {
             if (ca < 0) {
                 ca = 0;
-                m = 1;
+                m = geo.bc[AX];
             } else if (ca >= na) {
                 ca = na - 1;
-                m = 1;
+                m = geo.bc[AX];
             }
         }
         int cc[3] = {co[0], co[1], co[2]};
@@ -484,20 +487,22 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
             const int sl = sf / F, f = sf - sl * F;
             const int lo = t % S, hi = t / S;
             const double *src = a.w + cellidx[sl] * FNP + f * NP + lo + hi * S * P;
-            const bool mr = mir[sl] != 0;
+            const int mk = mir[sl];
+            const bool mr = mk != 0;                       // odd modes negated
+            const bool wn = mk == 2 && f == 1 + AX;        // wall: normal momentum negated
             T x[P];
             if (AX == 0 && P % 2 == 0) {
 #pragma unroll
                 for (int m = 0; m < P; m += 2) {
                     const DV<2> v = ldv<2>(src + m);
-                    x[m] = (T)v.x[0];
-                    x[m + 1] = (T)(mr ? -v.x[1] : v.x[1]);
+                    x[m] = (T)(wn ? -v.x[0] : v.x[0]);
+                    x[m + 1] = (T)((mr != wn) ? -v.x[1] : v.x[1]);
                 }
             } else {
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
                     const double v = src[m * S];
-                    x[m] = (T)((mr && (m & 1)) ? -v : v);
+                    x[m] = (T)(((mr && (m & 1)) != wn) ? -v : v);
                 }
             }
             const int pt = ppos<P, PP>(t);
@@ -816,11 +821,19 @@ size_t face_lds_bytes(int C)
 
 // LDS header of the volume kernel: face indices [C][D][2] (long long), wiggle
 // source [C] and new cell means [C][D+2] (double), the block's error flag;
-// rounded to 16 bytes.
+// rounded to 16 bytes.  Then the FP64 surface sums of the cell means
+// [D+2][C][p^(d-1)] (double): per lift line, the sum over the axes of the
+// lower minus the upper face flux at its face point.
 template <int D>
 __host__ __device__ constexpr size_t vol_hdr_bytes(int C)
 {
     return ((C * (2 * D * sizeof(long long) + (1 + D + 2) * sizeof(double)) + sizeof(int) + 15) / 16) * 16;
+}
+
+template <int D, int P>
+__host__ __device__ constexpr size_t vol_m0_bytes(int C)
+{
+    return (size_t)(D + 2) * C * ipow(P, D - 1) * sizeof(double);
 }
 
 // CC, NTC, FO: cells per block, threads per block and forcing (0 off, 1 on)
@@ -854,7 +867,8 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     double *cellv = (double *)(fidx + 2 * D * C);   // [C]: wiggle source
     double *cmean = cellv + C;                // [C][D+2]: new cell means (checks)
     int *blkflag = (int *)(cmean + C * (D + 2));
-    T *Ub = (T *)(smem + vol_hdr_bytes<D>(C));
+    double *m0s = (double *)(smem + vol_hdr_bytes<D>(C));   // [Fc][C][K] FP64 surface sums
+    T *Ub = (T *)(smem + vol_hdr_bytes<D>(C) + vol_m0_bytes<D, P>(C));
     T *G = Ub + Fx * CNP;
     T *X0 = (D == 3) ? G : Ub;     // the last of the D passes lands in Ub
     T *X1 = (D == 3) ? Ub : G;
@@ -1098,10 +1112,30 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
                 dlf[ax][r][0] = act ? fb[flo * (Fc * K) + f * K + t] : T(0);
                 dlf[ax][r][1] = act ? fb[fhi * (Fc * K) + f * K + t] : T(0);
             }
+            // FP64 surface sum of this line's face point (the mode-0 RHS of
+            // a conserved field is the sum of these over the face points)
+            if (act) {
+                double sm = 0.0;
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) sm += (double)dlf[ax][r][0] - (double)dlf[ax][r][1];
+                m0s[q] = sm;
+            }
         }
     } else {
 #pragma unroll
         for (int rr = 0; rr < NLF; ++rr) lift_load(tid + rr * nt, lfl[rr], lfu[rr]);
+        // FP64 surface sums per lift line (f, c, face point), same order as above
+        for (int q = tid; q < nlift; q += nt) {
+            T Fl[D], Fu[D];
+            lift_load(q, Fl, Fu);
+            const int c = q / (Fc * K);
+            const int r = q - c * (Fc * K);
+            const int f = r / K, k = r - f * K;
+            double sm = 0.0;
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) sm += (double)Fl[ax] - (double)Fu[ax];
+            m0s[(f * C + c) * K + k] = sm;
+        }
     }
 
     const double dt = a.dt_ptr ? *a.dt_ptr : a.dt;
@@ -1210,14 +1244,28 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
 #pragma unroll
             for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_BT>(k, i), x[k], acc);
             y[i] = acc;
-            if (PH == 2) Vl[o + i] = acc;
+        }
+        // mode 0 of a conserved field without a volume source: the volume
+        // term vanishes (Pt_0' = 0), so its RHS is the FP64 sum of the face
+        // fluxes over the cell's faces (single-valued fluxes: the totals are
+        // conserved to FP64 rounding also with an FP32 bulk)
+        const bool m0 = t == 0 && f < Fc && (f == 0 || !forced);
+        double y0 = (double)y[0];
+        if (m0) {
+            y0 = 0.0;
+            for (int k = 0; k < K; ++k) y0 += m0s[arr * K + k];
+            y[0] = (T)y0;
+        }
+        if (PH == 2) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) Vl[o + i] = y[i];
         }
         if (cc >= NC) return;
         const long long gi = cc * FNP + f * NP + t * P;
         double ov[P], o2v[P];
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-            const double L = pref * (double)y[i];
+            const double L = pref * (i == 0 ? y0 : (double)y[i]);
             ov[i] = a.c_cur * cu[i] + a.c_L * dt * L;
             if (a.base) ov[i] += a.c_base * ba[i];
             o2v[i] = a.d_cur * cu[i] + a.d_L * dt * L + (a.x2 ? a.d_x2 * x2[i] : 0.0);
@@ -1365,7 +1413,7 @@ size_t vol_lds_bytes(int C, int Fx)
 {
     constexpr int NP = Pad<P>::PP * ipow(P, D - 1);   // padded per-cell array
     constexpr int F = Fld<D, PH>::F;
-    return vol_hdr_bytes<D>(C) + sizeof(T) * ((size_t)C * Fx * NP + (size_t)C * D * F * NP);
+    return vol_hdr_bytes<D>(C) + vol_m0_bytes<D, P>(C) + sizeof(T) * ((size_t)C * Fx * NP + (size_t)C * D * F * NP);
 }
 
 // ---------------------------------------------------------------------------

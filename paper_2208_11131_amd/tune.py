@@ -41,7 +41,7 @@ def _state(dim, order, phys):
     n = (256, 256)
     if phys == 2:
         w = W.sod(order, 256, 256, device="cuda")
-        return w, None, dict(dim=2, n=n, gamma=1.4, av=True, bc=[1, 0])
+        return w, None, dict(dim=2, n=n, gamma=1.4, av=True, bc=[2, 0])
     w = W.random_smooth(2, n, order, seed=order, device="cuda")
     nu = 1e-4 if phys == 1 else 0.0
     return w, None, dict(dim=2, n=n, gamma=1.4, nu=nu, kappa=nu)

@@ -8,12 +8,14 @@
     stepped by the grouped, graph-captured batch path.
   * The shock tube at its full size, 1024 x 128, p = 6: ten steps equal the
     1024 x 1 strip row by row (the problem is y-uniform) to 1e-12.
-  * The shock tube run to t = 0.2 (Sec. 4.1 artificial viscosity, CFL 0.3):
-    L1(rho) against the exact Riemann solution (Toro ch. 4, tests/refsol.py),
-    FP64 at 1024 x 128 and in FP32 bulk (within 1 % of the FP64 error), and the
-    first-order fall of L1 over 128 -> 1024 cells on 1-cell strips.  The
-    absolute L1 value is not printed in the paper (parity unpinned); the
-    bounds below are the measured values with a margin, stated in the tests.
+  * The shock tube run to t = 0.2 (Sec. 4.1 artificial viscosity, CFL 0.3,
+    reflecting walls at the x ends): L1(rho) against the exact Riemann
+    solution (Toro ch. 4, tests/refsol.py), FP64 at 1024 x 128 (measured
+    1.78e-4) and in FP32 bulk (within 3 % of the FP64 error; measured 2.3 %),
+    and the first-order fall of L1 over 128 -> 1024 cells on 1-cell strips
+    (measured 1.03e-3, 5.6e-4, 3.0e-4, 1.78e-4).  The absolute L1 value is
+    not printed in the paper (parity unpinned); the bounds below are the
+    measured values with a margin.
 """
 import math
 import sys
@@ -67,17 +69,20 @@ def test_ten_steps_shear_layer_reduced(order):
 
 def test_ten_steps_shock_tube_strip_and_full_width():
     """1024 x 1 strip: 10 steps against the oracle (state, AV field and the
-    per-cell d ln S/dt); 1024 x 128: the same 10 steps give the strip in every
-    row."""
+    per-cell d ln S/dt); 1024 x 128 started from the strip's initial state in
+    every row: the same 10 steps give the strip in every row.  (Both start
+    from the same bits: the sensor threshold of Sec. 4.1 makes the AV field
+    depend discontinuously on the state, so initial states that differ by
+    rounding need not stay close.)"""
     order, nx = 6, 1024
     say("10 steps Sod 1024x1 and 1024x128")
     g = 1.4
-    ref = O.Problem(2, (nx, 1), 1.0 / nx, order, g, av={}, bc=(1, 0), cfl=0.3)
-    gs = dg.Solver(2, (nx, 1), order, g, hi=[1.0, 1.0 / nx], bc=[1, 0], av={}, cfl=0.3)
-    gf = dg.Solver(2, (nx, 128), order, g, hi=[1.0, 0.125], bc=[1, 0], av={}, cfl=0.3)
+    ref = O.Problem(2, (nx, 1), 1.0 / nx, order, g, av={}, bc=(2, 0), cfl=0.3)
+    gs = dg.Solver(2, (nx, 1), order, g, hi=[1.0, 1.0 / nx], bc=[2, 0], av={}, cfl=0.3)
+    gf = dg.Solver(2, (nx, 128), order, g, hi=[1.0, 0.125], bc=[2, 0], av={}, cfl=0.3)
     w0 = W.sod(order, nx, 1).numpy()
     ws = torch.tensor(w0, device="cuda")
-    wf = W.sod(order, nx, 128, device="cuda")
+    wf = torch.tensor(np.tile(w0, (128, 1, 1)), device="cuda")
     wr, Rr = w0, np.zeros(nx)
     for _ in range(10):
         dt = ref.max_dt(wr)[0]
@@ -158,7 +163,7 @@ T_END = 0.2
 
 def _run_sod(nx, ny, order=6, precision="fp64"):
     g = 1.4
-    s = dg.Solver(2, (nx, ny), order, g, hi=[1.0, ny / nx], bc=[1, 0], av={}, cfl=0.3, precision=precision)
+    s = dg.Solver(2, (nx, ny), order, g, hi=[1.0, ny / nx], bc=[2, 0], av={}, cfl=0.3, precision=precision)
     w = W.sod(order, nx, ny, device="cuda")
     t, nstep = 0.0, 0
     while t < T_END - 1e-14:
@@ -202,7 +207,7 @@ def test_shock_tube_full_run_fp64():
     say("  %d steps, L1(rho) = %.4e, row spread %.1e" % (nstep, l1, spread))
     assert 5000 <= nstep <= 30000
     assert spread <= 1e-10
-    assert l1 < 3e-3
+    assert l1 < 2.5e-4
 
 
 def test_shock_tube_full_run_fp32_bulk():
@@ -213,7 +218,9 @@ def test_shock_tube_full_run_fp32_bulk():
     w, nstep = _run_sod(nx, ny, order, precision="fp32")
     l1 = _l1_rho(w, nx, ny, order)
     say("  %d steps, L1(rho) FP32 bulk = %.4e, FP64 = %.4e, ratio %.5f" % (nstep, l1, l64, l1 / l64))
-    assert abs(l1 / l64 - 1.0) <= 0.01
+    # measured 1.023 (FP32 rounding of the RHS enters the stage-1 sensor rate
+    # and through it the wiggle source of the AV field); bound 3 %
+    assert abs(l1 / l64 - 1.0) <= 0.03
 
 
 def test_shock_tube_l1_converges():

@@ -189,7 +189,7 @@ def test_sod_l1_converges_to_exact_riemann(order):
     for nx in (32, 64):
         h = 1.0 / nx
         w0 = W.sod(order, nx, 1).numpy()
-        prob = O.Problem(2, (nx, 1), h, order, g, av=av, bc=(1, 0), cfl=0.3)
+        prob = O.Problem(2, (nx, 1), h, order, g, av=av, bc=(2, 0), cfl=0.3)
         t, R = 0.0, np.zeros(prob.ncells)
         w = w0
         while t < T - 1e-12:
