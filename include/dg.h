@@ -45,7 +45,8 @@ typedef enum {
     DG_EDEVICE = -3,        /* HIP runtime / launch error */
     DG_ENONPHYSICAL = -4,   /* a cell-mean density or pressure <= 0 (Sec. 4.2) */
     DG_ENONFINITE = -5,     /* a non-finite weight was produced */
-    DG_EUNSUPPORTED = -6    /* valid request this build does not implement */
+    DG_EUNSUPPORTED = -6,   /* valid request this build does not implement */
+    DG_ESCRATCH = -7        /* beyond the static scratch of dg_max_dt_noalloc */
 } dg_status;
 
 typedef enum { DG_BC_PERIODIC = 0, DG_BC_OUTFLOW = 1, DG_BC_WALL = 2 } dg_bc;
@@ -154,6 +155,21 @@ dg_status dg_step_cfl(dg_ctx *ctx, double *w, double *dt_dev, void *stream);
  * pointer.  cmax_out / vmax_out (host, may be NULL) receive the maxima. */
 dg_status dg_max_dt(dg_ctx *ctx, const double *w, double *dt_out, double *cmax_out, double *vmax_out,
                     void *stream);
+
+/* Allocation-free form of dg_max_dt, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Computes the same maxima and dt with the same kernels,
+ * but the per-block partial maxima live in a static device array of the
+ * library (64 KiB per device, taken at dg_init; at most 4096 partials, which
+ * every mesh meets: a larger request returns DG_ESCRATCH) instead of the
+ * context's buffer, and the result goes to a caller-owned DEVICE array out[3]
+ * = {dt, c_max, v_max} (8-byte aligned) instead of the host.  Enqueues two
+ * launches on `stream` and returns without waiting: no allocation, no copy,
+ * no synchronisation.  The current device must be the context's.  Every call
+ * on one device shares that device's array: calls that overlap in time on one
+ * device (different streams, threads or contexts) race and must be ordered by
+ * the caller. */
+dg_status dg_max_dt_noalloc(dg_ctx *ctx, const double *w, double *out, void *stream);
 
 /* Conserved totals sum_K |K| w_0 per conserved field (dim + 2 values, host
  * pointer `out`), deterministic compensated FP64 sums.  The integral of each

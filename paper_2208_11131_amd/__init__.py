@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgmi.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_ENONPHYSICAL, DG_ENONFINITE, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+DG_ESCRATCH = -7
 DG_BC_PERIODIC, DG_BC_OUTFLOW, DG_BC_WALL = 0, 1, 2
 DG_PREC_FP64, DG_PREC_FP32_BULK = 0, 1
 
@@ -60,6 +61,7 @@ _SIGS = {
     "dg_step": (ctypes.c_int, [_V, _V, ctypes.c_double, _V]),
     "dg_step_cfl": (ctypes.c_int, [_V, _V, _V, _V]),
     "dg_max_dt": (ctypes.c_int, [_V, _V, _D, _D, _D, _V]),
+    "dg_max_dt_noalloc": (ctypes.c_int, [_V, _V, _V, _V]),
     "dg_conserved_totals": (ctypes.c_int, [_V, _V, _D, _V]),
     "dg_set_forcing": (ctypes.c_int, [_V, _V]),
     "dg_set_sensor_rate": (ctypes.c_int, [_V, _V, _V]),
@@ -203,6 +205,12 @@ def dg_max_dt(ctx, w, stream=None):
     _chk(lib().dg_max_dt(ctx, _dptr(w, dg_state_len(ctx)), ctypes.byref(dt), ctypes.byref(cm),
                          ctypes.byref(vm), _stream(stream)), "dg_max_dt")
     return dt.value, cm.value, vm.value
+
+
+def dg_max_dt_noalloc(ctx, w, out, stream=None):
+    """out: float64 CUDA tensor of 3 elements, receives (dt, c_max, v_max)."""
+    _chk(lib().dg_max_dt_noalloc(ctx, _dptr(w, dg_state_len(ctx)), _dptr(out, 3), _stream(stream)),
+         "dg_max_dt_noalloc")
 
 
 def dg_conserved_totals(ctx, w, dim, stream=None):

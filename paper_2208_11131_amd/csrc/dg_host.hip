@@ -204,6 +204,8 @@ dg_status ensure_tables(int dev)
     return DG_OK;
 }
 
+dg_status ensure_scratch(int dev);
+
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
@@ -437,6 +439,37 @@ constexpr size_t LDS_MAX = 160 * 1024;
 // partial maxima the finalize reads, whatever the mesh size.
 constexpr int kCflBlocks = 4096;
 
+}  // namespace
+
+// Static scratch of the allocation-free entry point dg_max_dt_noalloc: the
+// CFL kernel's per-block (c_s, |v|) maxima, kScratchDoubles doubles (64 KiB).
+// Each device holds its own copy until the process ends.  In host code the
+// name stands for a host-side handle, not a device address: host code uses
+// g_scratch_dev[device] (from hipGetSymbolAddress at dg_init) instead.
+constexpr int kScratchDoubles = 2 * kCflBlocks;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (the current device), taken once
+// per device at context creation.
+dg_status ensure_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return DG_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_scratch_dev[dev]) return DG_OK;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return DG_EDEVICE;
+    }
+    g_scratch_dev[dev] = (double *)p;
+    return DG_OK;
+}
+
 constexpr long long EV_MAX = 16384;
 
 // Launch a kernel; with timing on, bracket it by a pair of events.
@@ -644,6 +677,7 @@ const char *dg_status_str(dg_status s)
     case DG_ENONPHYSICAL: return "non-positive cell-mean density or pressure";
     case DG_ENONFINITE: return "non-finite weight";
     case DG_EUNSUPPORTED: return "unsupported configuration";
+    case DG_ESCRATCH: return "request exceeds the static scratch of the allocation-free entry point";
     }
     return "unknown status";
 }
@@ -693,6 +727,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     int dev = 0;
     if (!ok(hipGetDevice(&dev))) return DG_EDEVICE;
     dg_status st = ensure_tables(dev);
+    if (st == DG_OK) st = ensure_scratch(dev);
     if (st != DG_OK) return st;
 
     dg_ctx *c = new (std::nothrow) dg_ctx;
@@ -980,6 +1015,33 @@ dg_status dg_max_dt(dg_ctx *c, const double *w, double *dt_out, double *cmax_out
     *dt_out = res[0];
     if (cmax_out) *cmax_out = res[1];
     if (vmax_out) *vmax_out = res[2];
+    return DG_OK;
+}
+
+dg_status dg_max_dt_noalloc(dg_ctx *c, const double *w, double *out, void *stream)
+{
+    if (!c || !w || !aligned16(w) || !out || ((uintptr_t)out & 7)) return DG_EINVAL;
+    int dev = -1;
+    if (!ok(hipGetDevice(&dev))) return DG_EDEVICE;
+    if (dev != c->device || dev < 0 || dev >= kMaxDevices || !g_scratch_dev[dev]) return DG_EINVAL;
+    if (2LL * c->cfl_blocks > kScratchDoubles) return DG_ESCRATCH;
+    hipStream_t s = (hipStream_t)stream;
+    double *part = g_scratch_dev[dev];
+    // every partial the finalize reads is written by the CFL launch before it
+    // (one per block), so nothing needs clearing
+    dgk::CflArgs ca;
+    ca.w = w;
+    ca.part = part;
+    ca.cells_per_block = c->cfl_C;
+    void *args[] = {&c->ph, &c->geo, &ca};
+    if (!ok(hipLaunchKernel(c->ks64.cfl, dim3((unsigned)c->cfl_blocks), dim3(c->cfl_T), args, c->cfl_lds, s)))
+        return DG_EDEVICE;
+    double num = c->cfl * c->ph.h / (2.0 * c->P);
+    const double *pp = part;
+    int nblk = c->cfl_blocks;
+    double *dt_copy = nullptr;
+    void *fargs[] = {&pp, &nblk, &out, &dt_copy, &num};
+    if (!ok(hipLaunchKernel((const void *)&cfl_finalize, dim3(1), dim3(kFinT), fargs, 0, s))) return DG_EDEVICE;
     return DG_OK;
 }
 
