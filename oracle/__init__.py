@@ -39,6 +39,7 @@ class Params(ctypes.Structure):
         ("f_tau", ctypes.c_double), ("f_w", ctypes.c_double), ("s_onset", ctypes.c_double),
         ("alpha_max", ctypes.c_double), ("cfl", ctypes.c_double),
         ("forcing", ctypes.POINTER(ctypes.c_double)),
+        ("limiter", ctypes.c_int),
     ]
 
 
@@ -68,6 +69,7 @@ def _load():
             "or_rk_stages": (ctypes.c_int, [ctypes.c_int]),
             "or_step": (None, [P, _D, ctypes.c_double, _D]),
             "or_totals": (None, [P, _D, _D]),
+            "or_limit": (ctypes.c_long, [P, _D]),
             "or_num_threads": (ctypes.c_int, []),
             "or_set_num_threads": (None, [ctypes.c_int]),
         }
@@ -90,7 +92,7 @@ class Problem:
     """Mesh, order and physics of one oracle run (mirrors the library's init)."""
 
     def __init__(self, dim, n, h, order, gamma, nu=0.0, kappa=0.0, bc=None, av=None,
-                 cfl=0.5, forcing=None):
+                 cfl=0.5, forcing=None, limiter=False):
         self.dim, self.order = dim, order
         self.n = tuple(n) + (1,) * (3 - len(n))
         self.h = h
@@ -102,6 +104,7 @@ class Problem:
         self.p.h, self.p.order = h, order
         self.p.gamma, self.p.nu, self.p.kappa = gamma, nu, kappa
         self.p.cfl = cfl
+        self.p.limiter = 1 if limiter else 0
         self.av = av
         if av is not None:
             self.p.av_on = 1
@@ -178,6 +181,13 @@ class Problem:
         cm, vm = ctypes.c_double(), ctypes.c_double()
         dt = lib.or_max_dt(ctypes.byref(self.p), _ptr(w), ctypes.byref(cm), ctypes.byref(vm))
         return dt, cm.value, vm.value
+
+    def limit(self, w):
+        """Positivity limiter (Sec. 4.2) on every cell; returns (w_new, cells changed)."""
+        lib = _load()
+        w = np.array(w, dtype=np.float64, order="C", copy=True)
+        n = lib.or_limit(ctypes.byref(self.p), _ptr(w))
+        return w, int(n)
 
     def totals(self, w):
         lib = _load()

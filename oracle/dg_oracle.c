@@ -799,6 +799,121 @@ void or_rhs_abs(const or_params *pr, const double *w, const double *R_prev, long
 }
 
 /* ------------------------------------------------------------------------- */
+/* Positivity limiter (Sec. 4.2)                                             */
+/* ------------------------------------------------------------------------- */
+
+#define OR_LIM_MAXHALF 60
+
+/* Points of the limiter: the volume Gauss points and the Gauss points of the
+ * 2d faces of the cell (xi_a = -1 or +1, the other coordinates Gauss nodes);
+ * edges and corners are not among them.  Writes xi[k*3 + b] and returns the
+ * count (p^d + 2 d p^(d-1)). */
+static int limiter_points(int p, int d, double *xi)
+{
+    double xg[OR_MAXP + 2], wg[OR_MAXP + 2];
+    or_gauss(p, xg, wg);
+    int np = 0;
+    const int M = ipow(p, d);
+    for (int j = 0; j < M; ++j) {
+        int jj[3];
+        mode_degrees(p, d, j, jj);
+        for (int b = 0; b < 3; ++b) xi[np * 3 + b] = b < d ? xg[jj[b]] : 0.0;
+        ++np;
+    }
+    const int K = ipow(p, d - 1);
+    for (int a = 0; a < d; ++a)
+        for (int side = -1; side <= 1; side += 2)
+            for (int k = 0; k < K; ++k) {
+                int kk = k;
+                for (int b = 0; b < d; ++b) {
+                    if (b == a) {
+                        xi[np * 3 + b] = (double)side;
+                    } else {
+                        xi[np * 3 + b] = xg[kk % p];
+                        kk /= p;
+                    }
+                }
+                for (int b = d; b < 3; ++b) xi[np * 3 + b] = 0.0;
+                ++np;
+            }
+    return np;
+}
+
+static double pressure_of(int d, double gamma, const double *u)
+{
+    double rho = u[0], v2 = 0.0;
+    for (int i = 0; i < d; ++i) v2 += (u[1 + i] / rho) * (u[1 + i] / rho);
+    return (gamma - 1.0) * (u[d + 1] - 0.5 * rho * v2);
+}
+
+/* Limit one cell in place (Sec. 4.2, after Zhang & Shu 2010 and Schaal et al.
+ * 2015).  With the cell means rho_bar and p_bar (p from the mean conserved
+ * values) both positive: if the density at any limiter point is below
+ * rho_bottom = 1e-6 rho_bar, every weight of degree >= 1 of every field is
+ * multiplied by (rho_bar - rho_bottom) / (rho_bar - rho_min); then, while the
+ * pressure at some limiter point is below p_bottom = 1e-6 p_bar, those weights
+ * are halved (at most OR_LIM_MAXHALF times, after which they are set to 0,
+ * leaving the cell mean).  Returns 1 if the cell was changed. */
+static int limit_cell(const or_params *pr, double *wc)
+{
+    const int p = pr->order, d = pr->dim, F = n_fields(pr), M = ipow(p, d);
+    double xi[3 * (OR_MAXP * OR_MAXP * OR_MAXP + 6 * OR_MAXP * OR_MAXP)];
+    const int np = limiter_points(p, d, xi);
+    double um[OR_MAXF];
+    for (int f = 0; f < F; ++f) um[f] = wc[f * M];
+    const double rbar = um[0], pbar = pressure_of(d, pr->gamma, um);
+    if (!(rbar > 0.0) || !(pbar > 0.0)) return 0;
+    int changed = 0;
+    /* density */
+    const double rb = 1e-6 * rbar;
+    double rmin = rbar;
+    for (int k = 0; k < np; ++k) {
+        double u[OR_MAXF];
+        eval_state(p, d, F, wc, xi + 3 * k, u, NULL);
+        if (u[0] < rmin) rmin = u[0];
+    }
+    if (rmin < rb) {
+        const double th = (rbar - rb) / (rbar - rmin);
+        for (int f = 0; f < F; ++f)
+            for (int m = 1; m < M; ++m) wc[f * M + m] *= th;
+        changed = 1;
+    }
+    /* pressure */
+    const double pb = 1e-6 * pbar;
+    for (int it = 0;; ++it) {
+        double pmin = pbar;
+        for (int k = 0; k < np; ++k) {
+            double u[OR_MAXF];
+            eval_state(p, d, F, wc, xi + 3 * k, u, NULL);
+            double pk = pressure_of(d, pr->gamma, u);
+            if (!(pk >= pmin)) pmin = pk;
+        }
+        if (pmin >= pb) break;
+        changed = 1;
+        if (it == OR_LIM_MAXHALF) {
+            for (int f = 0; f < F; ++f)
+                for (int m = 1; m < M; ++m) wc[f * M + m] = 0.0;
+            break;
+        }
+        for (int f = 0; f < F; ++f)
+            for (int m = 1; m < M; ++m) wc[f * M + m] *= 0.5;
+    }
+    return changed;
+}
+
+/* The limiter on every cell of w (in place); returns the number of cells
+ * changed. */
+long or_limit(const or_params *pr, double *w)
+{
+    const int F = n_fields(pr), M = ipow(pr->order, pr->dim);
+    const long NC = n_cells(pr);
+    long nchg = 0;
+#pragma omp parallel for reduction(+ : nchg) schedule(dynamic, 16)
+    for (long c = 0; c < NC; ++c) nchg += limit_cell(pr, w + c * (long)F * M);
+    return nchg;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Time step, RK, totals                                                      */
 /* ------------------------------------------------------------------------- */
 
@@ -839,9 +954,15 @@ int or_rk_stages(int order)
 
 /* One SSP-RK step of size dt in Shu-Osher form (Sec. 2.5).  R_state holds the
  * per-cell d ln S/dt of the previous step on entry and this step's on exit
- * (computed from the stage-1 state and its time derivative). */
+ * (computed from the stage-1 state and its time derivative).  With the
+ * positivity limiter on, every stage state and the result are limited. */
 void or_step(const or_params *pr, double *w, double dt, double *R_state)
 {
+/* the positivity limiter, when enabled, acts on every stage state (Sec. 4.2) */
+#define LIM(x) \
+    do {                                  \
+        if (pr->limiter) or_limit(pr, x); \
+    } while (0)
     const int p = pr->order, d = pr->dim, F = n_fields(pr), M = ipow(p, d);
     const long NC = n_cells(pr), N = NC * F * M;
     double *R_new = NULL;
@@ -853,21 +974,27 @@ void or_step(const or_params *pr, double *w, double dt, double *R_state)
     if (S == 1) {
         or_rhs(pr, u0, R_state, L, R_new);
         for (long i = 0; i < N; ++i) w[i] = u0[i] + dt * L[i];
+        LIM(w);
     } else if (S == 2) {
         double *u1 = (double *)malloc(sizeof(double) * N);
         or_rhs(pr, u0, R_state, L, R_new);
         for (long i = 0; i < N; ++i) u1[i] = u0[i] + dt * L[i];
+        LIM(u1);
         or_rhs(pr, u1, R_state, L, NULL);
         for (long i = 0; i < N; ++i) w[i] = 0.5 * u0[i] + 0.5 * (u1[i] + dt * L[i]);
+        LIM(w);
         free(u1);
     } else if (S == 3) {
         double *u1 = (double *)malloc(sizeof(double) * N), *u2 = (double *)malloc(sizeof(double) * N);
         or_rhs(pr, u0, R_state, L, R_new);
         for (long i = 0; i < N; ++i) u1[i] = u0[i] + dt * L[i];
+        LIM(u1);
         or_rhs(pr, u1, R_state, L, NULL);
         for (long i = 0; i < N; ++i) u2[i] = 0.75 * u0[i] + 0.25 * (u1[i] + dt * L[i]);
+        LIM(u2);
         or_rhs(pr, u2, R_state, L, NULL);
         for (long i = 0; i < N; ++i) w[i] = (1.0 / 3.0) * u0[i] + (2.0 / 3.0) * (u2[i] + dt * L[i]);
+        LIM(w);
         free(u1);
         free(u2);
     } else {
@@ -877,19 +1004,24 @@ void or_step(const or_params *pr, double *w, double dt, double *R_state)
         double *L3 = (double *)malloc(sizeof(double) * N);
         or_rhs(pr, u0, R_state, L, R_new);
         for (long i = 0; i < N; ++i) u1[i] = u0[i] + 0.391752226571890 * dt * L[i];
+        LIM(u1);
         or_rhs(pr, u1, R_state, L, NULL);
         for (long i = 0; i < N; ++i)
             u2[i] = 0.444370493651235 * u0[i] + 0.555629506348765 * u1[i] + 0.368410593050371 * dt * L[i];
+        LIM(u2);
         or_rhs(pr, u2, R_state, L, NULL);
         for (long i = 0; i < N; ++i)
             u3[i] = 0.620101851488403 * u0[i] + 0.379898148511597 * u2[i] + 0.251891774271694 * dt * L[i];
+        LIM(u3);
         or_rhs(pr, u3, R_state, L3, NULL);
         for (long i = 0; i < N; ++i)
             u4[i] = 0.178079954393132 * u0[i] + 0.821920045606868 * u3[i] + 0.544974750228521 * dt * L3[i];
+        LIM(u4);
         or_rhs(pr, u4, R_state, L, NULL);
         for (long i = 0; i < N; ++i)
             w[i] = 0.517231671970585 * u2[i] + 0.096059710526147 * u3[i] + 0.063692468666290 * dt * L3[i] +
                    0.386708617503269 * u4[i] + 0.226007483236906 * dt * L[i];
+        LIM(w);
         free(u1);
         free(u2);
         free(u3);
@@ -900,6 +1032,7 @@ void or_step(const or_params *pr, double *w, double dt, double *R_state)
     free(R_new);
     free(u0);
     free(L);
+#undef LIM
 }
 
 /* Conserved totals sum_K |K| w_0 per conserved field, Neumaier-compensated. */

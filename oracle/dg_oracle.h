@@ -18,6 +18,7 @@ typedef struct {
     double av_scale, f_v, f_tau, f_w, s_onset, alpha_max;
     double cfl;
     const double *forcing; /* [cell][3][p^d] coefficients of s, or NULL */
+    int limiter;       /* positivity limiter after every RK stage (Sec. 4.2) */
 } or_params;
 
 void or_legendre(int lmax, double x, double *Pt, double *dPt);
@@ -37,6 +38,7 @@ double or_max_dt(const or_params *pr, const double *w, double *cmax_out, double 
 int or_rk_stages(int order);
 void or_step(const or_params *pr, double *w, double dt, double *R_state);
 void or_totals(const or_params *pr, const double *w, double *out);
+long or_limit(const or_params *pr, double *w);
 int or_num_threads(void);
 void or_set_num_threads(int n);
 
