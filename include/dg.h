@@ -91,7 +91,9 @@ typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_BULK = 1 } dg_precision;
  * only basis of this build); cfl = f_CFL of eq. timestep (default 0.5);
  * launch tiles (0 = built-in tuned table): cells per volume block, faces per
  * face-kernel pencil, threads per volume / face block (multiples of 64,
- * at most 512).  Results do not depend on the tiles. */
+ * at most 512).  Results do not depend on the tiles.  limiter = 1: the
+ * positivity limiter of dg_limit acts on every state an RK stage writes
+ * (default 0; not available for batched ensembles). */
 typedef struct {
     int precision;
     int basis;
@@ -100,6 +102,7 @@ typedef struct {
     int faces_per_block;
     int vol_threads;
     int face_threads;
+    int limiter;
 } dg_options;
 
 void dg_av_defaults(dg_av_params *av);
@@ -149,6 +152,19 @@ dg_status dg_step(dg_ctx *ctx, double *w, double dt, void *stream);
  * device from w (eq. timestep) and never copied to the host; if dt_dev is
  * not NULL the step size (double) is also stored there (device pointer). */
 dg_status dg_step_cfl(dg_ctx *ctx, double *w, double *dt_dev, void *stream);
+
+/* Positivity limiter (Sec. 4.2) on w (device, in place), every cell: with
+ * positive mean density rho_bar and mean pressure p_bar (from the cell-mean
+ * conserved values), if the density at a limiter point (the volume Gauss
+ * points and the Gauss points of the cell's faces) is below rho_bottom =
+ * 1e-6 rho_bar, every weight of degree >= 1 of every field is multiplied by
+ * (rho_bar - rho_bottom) / (rho_bar - rho_min); then those weights are halved
+ * while the pressure at a limiter point is below 1e-6 p_bar (at most 60
+ * times, then they are set to 0).  Cell means never change; cells with a
+ * non-positive mean density or pressure are left alone.  With the `limiter`
+ * option the steps apply it to every stage state; the initial state is the
+ * caller's to limit (once, with this call).  FP64 in both precisions. */
+dg_status dg_limit(dg_ctx *ctx, double *w, void *stream);
 
 /* Time step of eq. timestep: maxima of the sound speed and of |v| over all
  * volume Gauss points of w.  Synchronises `stream`; *dt_out is a host
@@ -201,7 +217,8 @@ dg_status dg_get_tiles(const dg_ctx *ctx, int *vol_cells, int *vol_threads, int 
                        int *face_threads);
 
 /* Kernel timing (instrumentation): when enabled, every face, volume and CFL
- * kernel launch of this context is bracketed by HIP events recorded on its
+ * kernel launch of this context (the limiter counts as a CFL-kind launch)
+ * is bracketed by HIP events recorded on its
  * stream.  dg_timing_read synchronises on the last event, returns the summed
  * device milliseconds and launch counts per kernel kind since the last read
  * (host pointers, any may be NULL) and resets them.  At most 16384 launches

@@ -41,7 +41,7 @@ class dg_av_params(ctypes.Structure):
 class dg_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("basis", ctypes.c_int), ("cfl", ctypes.c_double),
                 ("cells_per_block", ctypes.c_int), ("faces_per_block", ctypes.c_int),
-                ("vol_threads", ctypes.c_int), ("face_threads", ctypes.c_int)]
+                ("vol_threads", ctypes.c_int), ("face_threads", ctypes.c_int), ("limiter", ctypes.c_int)]
 
 
 _V = ctypes.c_void_p
@@ -61,6 +61,7 @@ _SIGS = {
     "dg_step": (ctypes.c_int, [_V, _V, ctypes.c_double, _V]),
     "dg_step_cfl": (ctypes.c_int, [_V, _V, _V, _V]),
     "dg_max_dt": (ctypes.c_int, [_V, _V, _D, _D, _D, _V]),
+    "dg_limit": (ctypes.c_int, [_V, _V, _V]),
     "dg_max_dt_noalloc": (ctypes.c_int, [_V, _V, _V, _V]),
     "dg_conserved_totals": (ctypes.c_int, [_V, _V, _D, _V]),
     "dg_set_forcing": (ctypes.c_int, [_V, _V]),
@@ -198,6 +199,10 @@ def dg_step(ctx, w, dt, stream=None):
 def dg_step_cfl(ctx, w, dt_dev=None, stream=None):
     p = _dptr(dt_dev, 1) if dt_dev is not None else None
     _chk(lib().dg_step_cfl(ctx, _dptr(w, dg_state_len(ctx)), p, _stream(stream)), "dg_step_cfl")
+
+
+def dg_limit(ctx, w, stream=None):
+    _chk(lib().dg_limit(ctx, _dptr(w, dg_state_len(ctx)), _stream(stream)), "dg_limit")
 
 
 def dg_max_dt(ctx, w, stream=None):
@@ -349,7 +354,7 @@ class Solver:
 
     def __init__(self, dim, n, order, gamma, nu=0.0, kappa=0.0, lo=None, hi=None, bc=None, av=None,
                  precision="fp64", cfl=0.5, cells_per_block=0, faces_per_block=0, vol_threads=0,
-                 face_threads=0):
+                 face_threads=0, limiter=False):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the DG library runs on the GPU only")
         self.dim, self.order = dim, order
@@ -369,6 +374,7 @@ class Solver:
         opt.faces_per_block = faces_per_block
         opt.vol_threads = vol_threads
         opt.face_threads = face_threads
+        opt.limiter = 1 if limiter else 0
         self.ctx = dg_init(self.mesh, order, gamma, nu, kappa, avp, opt)
         self.nfields = dg_num_fields(self.ctx)
         self.ncells = 1
@@ -400,6 +406,9 @@ class Solver:
 
     def max_dt(self, w, stream=None):
         return dg_max_dt(self.ctx, w, stream)
+
+    def limit(self, w, stream=None):
+        dg_limit(self.ctx, w, stream)
 
     def totals(self, w, stream=None):
         return dg_conserved_totals(self.ctx, w, self.dim, stream)

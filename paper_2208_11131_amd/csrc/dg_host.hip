@@ -371,6 +371,9 @@ struct dg_ctx {
     int cfl_blocks;                // blocks (= partials) of a single-box CFL launch, at most kCflBlocks
     size_t vol_lds, vol_lds_forced, face_lds, cfl_lds;
     int stages;
+    int limiter;                   // positivity limiter after every stage (Sec. 4.2)
+    int lim_C, lim_T;
+    size_t lim_lds;
     double *reg[3];
     void *fb;
     size_t fb_bytes;
@@ -434,6 +437,19 @@ const void *get_face_fixed(int dim, int prec, int P, int phys, int C, int NT, in
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
+
+// Allow `bytes` of dynamic LDS for kernel fn.  A failure is returned and
+// cleared from the runtime's error state (nothing stale is left for the
+// caller's next HIP call to report).
+bool set_lds(const void *fn, size_t bytes)
+{
+    if (!fn) return false;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
 
 // Blocks of a single-box CFL launch (each loops over tiles): bounds the
 // partial maxima the finalize reads, whatever the mesh size.
@@ -571,7 +587,17 @@ dg_status run_cfl(dg_ctx *c, const double *w, double *dt_copy, hipStream_t s, bo
     return launch(c, 3, (const void *)&cfl_finalize, dim3(1), dim3(kFinT), fargs, 0, s);
 }
 
+// Positivity limiter (Sec. 4.2) on the state w, in place.
+dg_status run_limiter(dg_ctx *c, double *w, hipStream_t s)
+{
+    void *args[] = {&c->ph, &c->geo, &w, &c->lim_C};
+    dim3 g((unsigned)((c->ncells + c->lim_C - 1) / c->lim_C));
+    return launch(c, 4, c->ks64.limit, g, dim3(c->lim_T), args, c->lim_lds, s);
+}
+
 // SSP-RK step in Shu-Osher form; dt from the host value or a device pointer.
+// With the limiter on, every state a stage writes is limited (the partial sum
+// of the fourth 5-stage stage is not a state and is not limited).
 dg_status rk_step(dg_ctx *c, double *w, double dt, const double *dt_dev, hipStream_t s)
 {
     double *r1 = c->reg[0], *r2 = c->reg[1], *r3 = c->reg[2];
@@ -591,37 +617,42 @@ dg_status rk_step(dg_ctx *c, double *w, double dt, const double *dt_dev, hipStre
         v.check = 1;
         return v;
     };
+    auto lstage = [&](const dgk::VolArgs &v, hipStream_t st_) {
+        dg_status r = stage(c, v, st_);
+        if (r == DG_OK && c->limiter) r = run_limiter(c, v.out, st_);
+        return r;
+    };
     dg_status st = DG_OK;
     switch (c->stages) {
     case 1: {
         dgk::VolArgs v = A(w, nullptr, w, 0.0, 1.0, 1.0);
         v.R_out = Rn;
-        st = stage(c, v, s);
+        st = lstage(v, s);
         break;
     }
     case 2: {
         dgk::VolArgs v = A(w, nullptr, r1, 0.0, 1.0, 1.0);
         v.R_out = Rn;
-        if ((st = stage(c, v, s)) != DG_OK) break;
-        st = stage(c, A(r1, w, w, 0.5, 0.5, 0.5), s);
+        if ((st = lstage(v, s)) != DG_OK) break;
+        st = lstage(A(r1, w, w, 0.5, 0.5, 0.5), s);
         break;
     }
     case 3: {
         dgk::VolArgs v = A(w, nullptr, r1, 0.0, 1.0, 1.0);
         v.R_out = Rn;
-        if ((st = stage(c, v, s)) != DG_OK) break;
-        if ((st = stage(c, A(r1, w, r2, 0.75, 0.25, 0.25), s)) != DG_OK) break;
-        st = stage(c, A(r2, w, w, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0), s);
+        if ((st = lstage(v, s)) != DG_OK) break;
+        if ((st = lstage(A(r1, w, r2, 0.75, 0.25, 0.25), s)) != DG_OK) break;
+        st = lstage(A(r2, w, w, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0), s);
         break;
     }
     default: {
         // SSPRK(5,4), Spiteri & Ruuth (2002), Shu-Osher coefficients
         dgk::VolArgs v = A(w, nullptr, r1, 0.0, 1.0, 0.391752226571890);
         v.R_out = Rn;
-        if ((st = stage(c, v, s)) != DG_OK) break;
-        if ((st = stage(c, A(r1, w, r2, 0.444370493651235, 0.555629506348765, 0.368410593050371), s)) != DG_OK)
+        if ((st = lstage(v, s)) != DG_OK) break;
+        if ((st = lstage(A(r1, w, r2, 0.444370493651235, 0.555629506348765, 0.368410593050371), s)) != DG_OK)
             break;
-        if ((st = stage(c, A(r2, w, r3, 0.620101851488403, 0.379898148511597, 0.251891774271694), s)) != DG_OK)
+        if ((st = lstage(A(r2, w, r3, 0.620101851488403, 0.379898148511597, 0.251891774271694), s)) != DG_OK)
             break;
         // u4 -> r1 and the partial sum of the last stage -> w
         v = A(r3, w, r1, 0.178079954393132, 0.821920045606868, 0.544974750228521);
@@ -630,8 +661,8 @@ dg_status rk_step(dg_ctx *c, double *w, double dt, const double *dt_dev, hipStre
         v.d_x2 = 0.517231671970585;
         v.d_cur = 0.096059710526147;
         v.d_L = 0.063692468666290;
-        if ((st = stage(c, v, s)) != DG_OK) break;
-        st = stage(c, A(r1, w, w, 1.0, 0.386708617503269, 0.226007483236906), s);
+        if ((st = lstage(v, s)) != DG_OK) break;
+        st = lstage(A(r1, w, w, 1.0, 0.386708617503269, 0.226007483236906), s);
         break;
     }
     }
@@ -665,6 +696,7 @@ void dg_options_defaults(dg_options *opt)
     opt->faces_per_block = 0;
     opt->vol_threads = 0;
     opt->face_threads = 0;
+    opt->limiter = 0;
 }
 
 const char *dg_status_str(dg_status s)
@@ -840,6 +872,28 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     c->cfl_T = 256;
     while (c->cfl_C > 1 && c->ks64.cfl_lds(c->cfl_C, c->cfl_T) > 64 * 1024) --c->cfl_C;
     c->cfl_lds = c->ks64.cfl_lds(c->cfl_C, c->cfl_T);
+    c->limiter = o.limiter ? 1 : 0;
+    if (c->limiter) {
+        if (!c->ks64.limit) {
+            delete c;
+            return DG_EUNSUPPORTED;
+        }
+        // about 64 KiB of LDS per block: two extended-grid arrays per cell
+        size_t per_cell = c->ks64.limit_lds(1, 256) - c->ks64.limit_lds(0, 256);
+        c->lim_C = (int)std::max<size_t>(1, (64 * 1024) / std::max<size_t>(per_cell, 1));
+        if (c->lim_C > 256) c->lim_C = 256;
+        if (c->lim_C > c->ncells) c->lim_C = (int)c->ncells;
+        c->lim_T = 256;
+        c->lim_lds = c->ks64.limit_lds(c->lim_C, c->lim_T);
+        if (c->lim_lds > LDS_MAX) {
+            delete c;
+            return DG_EUNSUPPORTED;
+        }
+        if (!set_lds(c->ks64.limit, c->lim_lds)) {
+            delete c;
+            return DG_EDEVICE;
+        }
+    }
     c->cfl_tiles = (int)((c->ncells + c->cfl_C - 1) / c->cfl_C);
     c->cfl_blocks = std::min(c->cfl_tiles, kCflBlocks);
     if (c->face_lds > LDS_MAX || c->cfl_lds > LDS_MAX) {
@@ -847,17 +901,17 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         return DG_EUNSUPPORTED;
     }
     const size_t lim = LDS_MAX;
-    (void)hipFuncSetAttribute(c->ks.vol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+    (void)set_lds(c->ks.vol, lim);
     for (int fo = 0; fo < 2; ++fo) {
         c->vol_fixed[fo] = get_vol_fixed(d, c->precision, order, c->phys, c->vol_C, c->vol_T, fo);
         if (c->vol_fixed[fo])
-            (void)hipFuncSetAttribute(c->vol_fixed[fo], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+            (void)set_lds(c->vol_fixed[fo], lim);
     }
-    (void)hipFuncSetAttribute(c->ks.face, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+    (void)set_lds(c->ks.face, lim);
     c->face_fixed = get_face_fixed(d, c->precision, order, c->phys, c->face_C, c->face_T);
     if (c->face_fixed)
-        (void)hipFuncSetAttribute(c->face_fixed, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
-    (void)hipFuncSetAttribute(c->ks64.cfl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+        (void)set_lds(c->face_fixed, lim);
+    (void)set_lds(c->ks64.cfl, lim);
 
     // buffers
     const size_t nstate = (size_t)c->ncells * c->F * c->NP;
@@ -1001,6 +1055,24 @@ dg_status dg_step_cfl(dg_ctx *c, double *w, double *dt_dev, void *stream)
     if (st == DG_OK) st = rk_step(c, w, 0.0, c->scal, s);
     c->fin_pending = false;
     return st;
+}
+
+dg_status dg_limit(dg_ctx *c, double *w, void *stream)
+{
+    if (!c || !w || ((uintptr_t)w & 7)) return DG_EINVAL;
+    if (!c->ks64.limit) return DG_EUNSUPPORTED;
+    if (!c->limiter) {
+        // limiter tiles of a context created without the option
+        size_t per_cell = c->ks64.limit_lds(1, 256) - c->ks64.limit_lds(0, 256);
+        c->lim_C = (int)std::max<size_t>(1, (64 * 1024) / std::max<size_t>(per_cell, 1));
+        if (c->lim_C > 256) c->lim_C = 256;
+        if (c->lim_C > c->ncells) c->lim_C = (int)c->ncells;
+        c->lim_T = 256;
+        c->lim_lds = c->ks64.limit_lds(c->lim_C, c->lim_T);
+        if (c->lim_lds > LDS_MAX) return DG_EUNSUPPORTED;
+        if (!set_lds(c->ks64.limit, c->lim_lds)) return DG_EDEVICE;
+    }
+    return run_limiter(c, w, (hipStream_t)stream);
 }
 
 dg_status dg_max_dt(dg_ctx *c, const double *w, double *dt_out, double *cmax_out, double *vmax_out, void *stream)
@@ -1266,6 +1338,7 @@ static dg_status batch_init_impl(int nbox, const dg_mesh *meshes, const int *ord
     *out = nullptr;
     if (nbox < 1 || !meshes || !orders) return DG_EINVAL;
     if (av && av->enabled) return DG_EUNSUPPORTED;
+    if (opt && opt->limiter) return DG_EUNSUPPORTED;
     for (int i = 0; i < nbox; ++i)
         if (meshes[i].dim != meshes[0].dim) return DG_EINVAL;
     dg_batch *b = new (std::nothrow) dg_batch;
@@ -1322,9 +1395,9 @@ static dg_status batch_init_impl(int nbox, const dg_mesh *meshes, const int *ord
         if (!g.ks.vol_b || !g.ks.face_b || !g.ks64.cfl_b) {
             return DG_EUNSUPPORTED;
         }
-        (void)hipFuncSetAttribute(g.ks.vol_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
-        (void)hipFuncSetAttribute(g.ks.face_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
-        (void)hipFuncSetAttribute(g.ks64.cfl_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+        (void)set_lds(g.ks.vol_b, LDS_MAX);
+        (void)set_lds(g.ks.face_b, LDS_MAX);
+        (void)set_lds(g.ks64.cfl_b, LDS_MAX);
         for (int i : g.boxes) {
             const dg_ctx *c = b->box[i];
             dgk::BoxDesc d;

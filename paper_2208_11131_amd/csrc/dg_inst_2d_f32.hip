@@ -18,6 +18,8 @@ void fill(KernelSet *k)
     k->cfl = nullptr;
     k->cfl_b = nullptr;
     k->cfl_lds = nullptr;
+    k->limit = nullptr;
+    k->limit_lds = nullptr;
 }
 
 template <int P>

@@ -18,6 +18,8 @@ void fill(KernelSet *k)
     k->cfl = (const void *)&cfl_kernel<2, P, PH>;
     k->cfl_b = (const void *)&cfl_kernel_batched<2, P, PH>;
     k->cfl_lds = &cfl_lds_bytes<2, P>;
+    k->limit = (const void *)&limit_kernel<2, P, PH>;
+    k->limit_lds = &lim_lds_bytes<2, P>;
 }
 
 template <int P>

@@ -1557,6 +1557,241 @@ size_t cfl_lds_bytes(int C, int nt)
 }
 
 // ---------------------------------------------------------------------------
+// positivity limiter (Sec. 4.2), FP64 on the FP64 state
+// ---------------------------------------------------------------------------
+//
+// One block = C consecutive cells.  The conserved fields are evaluated on the
+// extended grid of E = p + 2 nodes per axis (-1, the p Gauss nodes, +1) by one
+// E x p operator pass per axis; the limiter points are the grid points with at
+// most one coordinate at -1 or +1 (the volume Gauss points and the Gauss
+// points of the 2d faces).  Per cell: rho_min over the points; if below
+// rho_bottom = 1e-6 rho_bar the weights of degree >= 1 of every field get the
+// factor theta = (rho_bar - rho_bottom) / (rho_bar - rho_min); then theta is
+// halved while the pressure of u_bar + theta (u - u_bar) at some point is
+// below 1e-6 p_bar (at most kLimHalvings times, then the weights are zeroed).
+// Cells whose mean density or pressure is not positive are left alone (the
+// stage check flags them).  Only the cells that change are written.
+
+constexpr int kLimHalvings = 60;
+
+// 1D value of mode l at extended node j (0: -1, 1..P: Gauss, P+1: +1)
+template <int P>
+__device__ __forceinline__ double ext_val(const Tab<double> &t, int l, int j)
+{
+    return j == 0 ? t.em[l] : (j == P + 1 ? t.ep[l] : t.B[l][j - 1]);
+}
+
+template <int D, int P>
+struct LimGeo {
+    static constexpr int E = P + 2;
+    static constexpr int NE = ipow(E, D);            // extended grid points per cell
+    static constexpr int Fc = D + 2;
+};
+
+template <int D, int P>
+__host__ __device__ constexpr size_t lim_lds_bytes(int C, int nt)
+{
+    // two ping-pong arrays [Fc][C][E^D], per-(cell, lane) partial minima,
+    // per-cell theta / status
+    return sizeof(double) * (2 * (size_t)(D + 2) * C * ipow(P + 2, D) + (size_t)nt + 2 * (size_t)C) + 16;
+}
+
+template <int D, int P, int PH>
+__device__ __forceinline__ void limit_tile(const Phys &ph, const Geo &geo, double *__restrict__ w,
+                                           unsigned char *smem, int C, long long tile)
+{
+    constexpr int E = LimGeo<D, P>::E, NE = LimGeo<D, P>::NE, Fc = D + 2;
+    constexpr int NP = ipow(P, D);
+    constexpr int F = Fld<D, PH>::F;
+    constexpr int FNP = F * NP;
+    const Tab<double> &tb = TabSel<double>::get(P);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const long long NC = geo.ncells;
+    const long long c0 = tile * C;
+    const int CN = C * NE;                           // one field of the tile
+    double *X = (double *)smem;                      // [Fc][C][NE]
+    double *Y = X + (size_t)Fc * CN;
+    double *red = Y + (size_t)Fc * CN;               // [nt]
+    double *theta = red + nt;                        // [C]
+    double *stat = theta + C;                        // [C]: 1 = still halving
+    int *more_flag = (int *)(stat + C);              // some cell still halving
+    // pass along x: line (f, c, t), t = transverse mode (l_y[, l_z]); output
+    // index ((f C + c) p^(d-1) + t) E + j_x
+    constexpr int K = NP / P;
+    for (int q = tid; q < Fc * C * K; q += nt) {
+        const int arr = q / K, t = q - arr * K;
+        const int f = arr / C, c = arr - f * C;
+        long long cc = c0 + c;
+        if (cc >= NC) cc = NC - 1;
+        const double *src = w + cc * FNP + f * NP + t * P;
+        double x[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = src[k];
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) acc = fma(ext_val<P>(tb, k, j), x[k], acc);
+            Y[q * E + j] = acc;
+        }
+    }
+    __syncthreads();
+    // pass along y: line (f, c, l_z, j_x): P values at stride E -> E values at
+    // stride E; output ((f C + c) p^(d-2) + l_z) E^2 + j_y E + j_x
+    constexpr int KZ = (D == 3) ? P : 1;
+    for (int q = tid; q < Fc * C * KZ * E; q += nt) {
+        const int jx = q % E, r = q / E;             // r = (f C + c) KZ + l_z
+        const double *in = Y + (size_t)r * P * E + jx;
+        double x[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = in[k * E];
+        double *out = X + (size_t)r * E * E + jx;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) acc = fma(ext_val<P>(tb, k, j), x[k], acc);
+            out[j * E] = acc;
+        }
+    }
+    __syncthreads();
+    const double *V = X;
+    if (D == 3) {
+        // pass along z: line (f, c, j_y, j_x): P values at stride E^2
+        for (int q = tid; q < Fc * C * E * E; q += nt) {
+            const int jxy = q % (E * E), arr = q / (E * E);
+            const double *in = X + (size_t)arr * P * E * E + jxy;
+            double x[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) x[k] = in[k * E * E];
+            double *out = Y + (size_t)arr * NE + jxy;
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) acc = fma(ext_val<P>(tb, k, j), x[k], acc);
+                out[j * E * E] = acc;
+            }
+        }
+        __syncthreads();
+        V = Y;
+    }
+    // lanes per cell for the per-cell minima (block size is a multiple of 64)
+    const int S = nt / C > 0 ? nt / C : 1;
+    const int cl = tid / S, sl = tid - cl * S;
+    auto is_point = [&](int j) {
+        int ends = 0, r = j;
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            const int jb = r % E;
+            r /= E;
+            ends += (jb == 0 || jb == E - 1) ? 1 : 0;
+        }
+        return ends <= 1;
+    };
+    auto cell_means = [&](int c, double *um) {
+        long long cc = c0 + c;
+        if (cc >= NC) cc = NC - 1;
+#pragma unroll
+        for (int f = 0; f < Fc; ++f) um[f] = w[cc * FNP + f * NP];
+    };
+    // minimum in which NaN counts as lower than anything (a NaN pressure must
+    // be limited)
+    auto lowest = [](double a, double b) { return (b >= a || a != a) ? a : b; };
+    auto pres = [&](const double *u) {
+        const double rho = u[0];
+        double v2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double v = u[1 + i] / rho;
+            v2 += v * v;
+        }
+        return (ph.gamma - 1.0) * (u[D + 1] - 0.5 * rho * v2);
+    };
+    // density minima
+    double rmin = 1.0 / 0.0;
+    if (cl < C)
+        for (int j = sl; j < NE; j += S)
+            if (is_point(j)) rmin = fmin(rmin, V[cl * NE + j]);
+    red[tid] = rmin;
+    __syncthreads();
+    for (int c = tid; c < C; c += nt) {
+        double m = red[c * S];
+        for (int k = 1; k < S; ++k) m = fmin(m, red[c * S + k]);
+        double um[Fc];
+        cell_means(c, um);
+        const double rbar = um[0], pbar = pres(um);
+        double th = 1.0, st = 0.0;
+        if (rbar > 0.0 && pbar > 0.0 && c0 + c < NC) {
+            const double rb = 1e-6 * rbar;
+            if (m < rb) th = (rbar - rb) / (rbar - m);
+            st = 1.0;                                // pressure stage to do
+        }
+        theta[c] = th;
+        stat[c] = st;
+    }
+    __syncthreads();
+    // pressure: halve theta while some point is below p_bottom (block-uniform
+    // loop, at most kLimHalvings + 1 evaluations)
+    for (int it = 0; it <= kLimHalvings; ++it) {
+        double pmin = 1.0 / 0.0;
+        if (cl < C && stat[cl] != 0.0) {
+            double um[Fc];
+            cell_means(cl, um);
+            const double th = theta[cl];
+            for (int j = sl; j < NE; j += S)
+                if (is_point(j)) {
+                    double u[Fc];
+#pragma unroll
+                    for (int f = 0; f < Fc; ++f) u[f] = um[f] + th * (V[(f * C + cl) * NE + j] - um[f]);
+                    const double pk = pres(u);
+                    pmin = lowest(pmin, pk);
+                }
+        }
+        red[tid] = pmin;
+        if (tid == 0) *more_flag = 0;
+        __syncthreads();
+        for (int c = tid; c < C; c += nt) {
+            if (stat[c] == 0.0) continue;
+            double m = red[c * S];
+            for (int k = 1; k < S; ++k) m = lowest(m, red[c * S + k]);
+            double um[Fc];
+            cell_means(c, um);
+            const double pb = 1e-6 * pres(um);
+            if (m >= pb) {
+                stat[c] = 0.0;
+            } else if (it == kLimHalvings) {
+                theta[c] = 0.0;
+                stat[c] = 0.0;
+            } else {
+                theta[c] *= 0.5;
+                *more_flag = 1;
+            }
+        }
+        // block-uniform continuation: any cell still halving
+        __syncthreads();
+        const int more = *more_flag;
+        __syncthreads();                             // read before the next reset
+        if (!more) break;
+    }
+    // write the limited cells: weights of degree >= 1 of every field
+    for (int q = tid; q < C * F * NP; q += nt) {
+        const int c = q / (F * NP), r = q - c * (F * NP);
+        if (r % NP == 0) continue;                   // the mean
+        const double th = theta[c];
+        const long long cc = c0 + c;
+        if (th < 1.0 && cc < NC) w[cc * FNP + r] *= th;
+    }
+}
+
+template <int D, int P, int PH>
+__global__ void __launch_bounds__(512) limit_kernel(Phys ph, Geo geo, double *w, int C)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    limit_tile<D, P, PH>(ph, geo, w, smem, C, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // fixed-tile volume kernels of the tuned table
 // ---------------------------------------------------------------------------
 

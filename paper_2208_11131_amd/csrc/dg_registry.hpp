@@ -19,6 +19,8 @@ struct KernelSet {
     size_t (*vol_lds)(int C, int Fx);
     size_t (*face_lds)(int C);
     size_t (*cfl_lds)(int C, int nt);
+    const void *limit;     // positivity limiter (FP64 units only)
+    size_t (*limit_lds)(int C, int nt);
 };
 
 void dgk_get_2d_f64(int P, int ph, KernelSet *k);

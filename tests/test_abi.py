@@ -66,6 +66,8 @@ def test_init_rejects_invalid_arguments(case):
     assert r == dg.DG_EINVAL and not ctx.value
     assert dg.lib().dg_rhs(None, None, None, None) == dg.DG_EINVAL
     assert dg.lib().dg_step(None, None, 1.0, None) == dg.DG_EINVAL
+    assert dg.lib().dg_limit(None, None, None) == dg.DG_EINVAL
+    assert dg.lib().dg_max_dt_noalloc(None, None, None, None) == dg.DG_EINVAL
 
 
 def test_init_rejects_meshes_beyond_the_index_limit():
