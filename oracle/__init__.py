@@ -40,6 +40,7 @@ class Params(ctypes.Structure):
         ("alpha_max", ctypes.c_double), ("cfl", ctypes.c_double),
         ("forcing", ctypes.POINTER(ctypes.c_double)),
         ("limiter", ctypes.c_int),
+        ("tracer", ctypes.c_int), ("eta", ctypes.c_double),
     ]
 
 
@@ -92,7 +93,7 @@ class Problem:
     """Mesh, order and physics of one oracle run (mirrors the library's init)."""
 
     def __init__(self, dim, n, h, order, gamma, nu=0.0, kappa=0.0, bc=None, av=None,
-                 cfl=0.5, forcing=None, limiter=False):
+                 cfl=0.5, forcing=None, limiter=False, tracer=False, eta=0.0):
         self.dim, self.order = dim, order
         self.n = tuple(n) + (1,) * (3 - len(n))
         self.h = h
@@ -105,6 +106,8 @@ class Problem:
         self.p.gamma, self.p.nu, self.p.kappa = gamma, nu, kappa
         self.p.cfl = cfl
         self.p.limiter = 1 if limiter else 0
+        self.p.tracer = 1 if tracer else 0
+        self.p.eta = eta
         self.av = av
         if av is not None:
             self.p.av_on = 1
@@ -115,7 +118,8 @@ class Problem:
             self.p.s_onset = av.get("s_onset", 1e-4)
             self.p.alpha_max = av.get("alpha_max", 1.0)
         self.set_forcing(forcing)
-        self.nfields = dim + 2 + (1 if av is not None else 0)
+        self.ncons = dim + 2 + (1 if tracer else 0)
+        self.nfields = self.ncons + (1 if av is not None else 0)
         self.nmodes = order ** dim
         self.ncells = int(np.prod(self.n[:dim]))
 
@@ -192,7 +196,7 @@ class Problem:
     def totals(self, w):
         lib = _load()
         w = np.ascontiguousarray(w, dtype=np.float64)
-        out = np.zeros(self.dim + 2)
+        out = np.zeros(self.ncons)
         lib.or_totals(ctypes.byref(self.p), _ptr(w), _ptr(out))
         return out
 

@@ -125,9 +125,16 @@ static int ipow(int b, int e)
     return r;
 }
 
+/* Conserved fields: rho, rho v, e (dim + 2) and, with the passive tracer,
+ * c rho (Sec. 3.4).  All of them carry face fluxes. */
+static int n_cons(const or_params *pr)
+{
+    return pr->dim + 2 + (pr->tracer ? 1 : 0);
+}
+
 static int n_fields(const or_params *pr)
 {
-    return pr->dim + 2 + (pr->av_on ? 1 : 0);
+    return n_cons(pr) + (pr->av_on ? 1 : 0);
 }
 
 static long n_cells(const or_params *pr)
@@ -252,15 +259,32 @@ void or_euler_flux(int d, double gamma, const double *u, int a, double *f)
     f[d + 1] = (E + pres) * v[a];
 }
 
+/* Flux along axis a of the nc conserved fields: the Euler flux and, for a
+ * passive tracer (nc = d + 3), its advective flux c rho v_a (Sec. 3.4). */
+static void cons_flux(int d, int nc, double gamma, const double *u, int a, double *f)
+{
+    or_euler_flux(d, gamma, u, a, f);
+    if (nc > d + 2) f[d + 2] = u[d + 2] * u[1 + a] / u[0];
+}
+
+static void hllc_n(int d, int nc, double gamma, const double *uL, const double *uR, int a, double *F);
+
 /* HLLC flux F(uL, uR) along axis a (Toro, Riemann Solvers, ch. 10), with Davis
  * wave-speed estimates; branch choice 0<=SL -> FL, SL<0<=S* -> F*L,
  * S*<0<SR -> F*R, else FR. */
 void or_hllc(int d, double gamma, const double *uL, const double *uR, int a, double *F)
 {
-    const int Fc = d + 2;
-    double fL[5], fR[5];
-    or_euler_flux(d, gamma, uL, a, fL);
-    or_euler_flux(d, gamma, uR, a, fR);
+    hllc_n(d, d + 2, gamma, uL, uR, a, F);
+}
+
+/* The same for nc conserved fields: a passive scalar's star state is the
+ * side's concentration times the star density (Toro ch. 10). */
+static void hllc_n(int d, int nc, double gamma, const double *uL, const double *uR, int a, double *F)
+{
+    const int Fc = nc;
+    double fL[6], fR[6];
+    cons_flux(d, nc, gamma, uL, a, fL);
+    cons_flux(d, nc, gamma, uR, a, fR);
     double rL = uL[0], rR = uR[0];
     double vL2 = 0, vR2 = 0;
     for (int i = 0; i < d; ++i) {
@@ -289,10 +313,11 @@ void or_hllc(int d, double gamma, const double *uL, const double *uR, int a, dou
     double r = u[0], un = u[1 + a] / r;
     double pK = (Ss >= 0.0) ? pL : pR;
     double fac = r * (S - un) / (S - Ss);
-    double us[5];
+    double us[6];
     us[0] = fac;
     for (int i = 0; i < d; ++i) us[1 + i] = (i == a) ? fac * Ss : fac * (u[1 + i] / r);
     us[d + 1] = fac * (u[d + 1] / r + (Ss - un) * (Ss + pK / (r * (S - un))));
+    if (nc > d + 2) us[d + 2] = fac * (u[d + 2] / r);
     for (int k = 0; k < Fc; ++k) F[k] = fK[k] + S * (us[k] - u[k]);
 }
 
@@ -301,6 +326,19 @@ void or_hllc(int d, double gamma, const double *uL, const double *uR, int a, dou
  * Pi = nu rho (grad v + grad v^T - 2/3 div v I) and primitive gradients from
  * conserved ones, grad v = (grad(rho v) - v grad rho) / rho.
  * g[b*Fs + f] = d u_f / d x_b (physical derivatives). */
+static void ns_flux(int d, double gamma, double nu, double chi, const double *u, const double *g, int Fs,
+                    int a, double *fv);
+
+/* The diffusive flux of all conserved fields: Navier-Stokes (above) and, with
+ * the passive tracer, eta rho d_a c = eta (d_a(c rho) - c d_a rho)
+ * (Sec. 3.4 eq. passivetracer). */
+static void diff_flux(const or_params *pr, const double *u, const double *g, int Fs, int a, double *fv)
+{
+    const int d = pr->dim;
+    ns_flux(d, pr->gamma, pr->nu, pr->kappa, u, g, Fs, a, fv);
+    if (pr->tracer) fv[d + 2] = pr->eta * (g[a * Fs + d + 2] - (u[d + 2] / u[0]) * g[a * Fs + 0]);
+}
+
 static void ns_flux(int d, double gamma, double nu, double chi, const double *u, const double *g, int Fs,
                     int a, double *fv)
 {
@@ -344,9 +382,15 @@ static double av_eps(const or_params *pr, double alpha, double cs)
     return pr->av_scale * a * cs * pr->h / pr->order;
 }
 
+/* Diffusive (Navier-Stokes / tracer) terms present. */
+static int need_diff(const or_params *pr)
+{
+    return pr->nu > 0.0 || pr->kappa > 0.0 || (pr->tracer && pr->eta > 0.0);
+}
+
 static int need_grad(const or_params *pr)
 {
-    return pr->nu > 0.0 || pr->kappa > 0.0 || pr->av_on;
+    return need_diff(pr) || pr->av_on;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -465,14 +509,14 @@ void or_recover_face(const or_params *pr, const double *wL, const double *wR, in
  * F = F_K + S_K (U*_K - U_K) on either side K, so the rounding of F is bounded
  * by a multiple of |F_L| + |F_R| + |S_L| (|U*_L| + |U_L|) + |S_R| (|U*_R| + |U_R|)
  * (both sides: the branch may flip where S* crosses 0). */
-static void hllc_terms_abs(int d, double gamma, const double *uL, const double *uR, int a, double *A)
+static void hllc_terms_abs(int d, int nc, double gamma, const double *uL, const double *uR, int a, double *A)
 {
-    const int Fc = d + 2;
-    double fL[5], fR[5];
-    or_euler_flux(d, gamma, uL, a, fL);
-    or_euler_flux(d, gamma, uR, a, fR);
+    const int Fc = nc;
+    double fL[6], fR[6];
+    cons_flux(d, nc, gamma, uL, a, fL);
+    cons_flux(d, nc, gamma, uR, a, fR);
     const double *u2[2] = {uL, uR};
-    double S[2], us[2][5];
+    double S[2], us[2][6];
     double rL = uL[0], rR = uR[0], vL2 = 0, vR2 = 0;
     for (int i = 0; i < d; ++i) {
         vL2 += (uL[1 + i] / rL) * (uL[1 + i] / rL);
@@ -493,6 +537,7 @@ static void hllc_terms_abs(int d, double gamma, const double *uL, const double *
         us[sd][0] = fac;
         for (int i = 0; i < d; ++i) us[sd][1 + i] = (i == a) ? fac * Ss : fac * (u[1 + i] / r);
         us[sd][d + 1] = fac * (u[d + 1] / r + (Ss - un) * (Ss + pK / (r * (S[sd] - un))));
+        if (nc > d + 2) us[sd][d + 2] = fac * (u[d + 2] / r);
     }
     for (int k = 0; k < Fc; ++k)
         A[k] = fabs(fL[k]) + fabs(fR[k]) + fabs(S[0]) * (fabs(us[0][k]) + fabs(uL[k])) +
@@ -512,7 +557,7 @@ static void face_flux(const or_params *pr, const double *wL, const double *wR, i
 
 static void face_flux_m(const or_params *pr, const double *wL, const double *wR, int a, double *Fh, int absmode)
 {
-    const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = d + 2;
+    const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = n_cons(pr);
     double xg[OR_MAXP + 2], wg[OR_MAXP + 2];
     or_gauss(p, xg, wg);
     int tdim[2], nt = 0;
@@ -538,15 +583,15 @@ static void face_flux_m(const or_params *pr, const double *wL, const double *wR,
         xi[a] = -1.0;
         eval_state(p, d, F, wR, xi, uR, NULL);
         if (absmode)
-            hllc_terms_abs(d, pr->gamma, uL, uR, a, Fh + k * Fc);
+            hllc_terms_abs(d, Fc, pr->gamma, uL, uR, a, Fh + k * Fc);
         else
-            or_hllc(d, pr->gamma, uL, uR, a, Fh + k * Fc);
+            hllc_n(d, Fc, pr->gamma, uL, uR, a, Fh + k * Fc);
         if (need_grad(pr)) {
             const double *u = ut + k * F;
             const double *g = gt + k * d * F;
-            if (pr->nu > 0.0 || pr->kappa > 0.0) {
-                double fv[5];
-                ns_flux(d, pr->gamma, pr->nu, pr->kappa, u, g, F, a, fv);
+            if (need_diff(pr)) {
+                double fv[6];
+                diff_flux(pr, u, g, F, a, fv);
                 for (int f = 0; f < Fc; ++f) Fh[k * Fc + f] += absmode ? fabs(fv[f]) : -fv[f];
             }
             if (pr->av_on) {
@@ -618,7 +663,7 @@ double or_sensor_rate(int p, int d, const double *wrho, const double *wdrho)
 static void rhs_cell(const or_params *pr, const double *w, const double *R_prev, long c, double *out,
                      double *R_out_c, int absmode)
 {
-    const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = d + 2;
+    const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = n_cons(pr);
     const int M = ipow(p, d), NP = M;
     const double h = pr->h;
     const double pref = pow(2.0, 1 - d) / h;     /* 2^(1-d)/h */
@@ -649,12 +694,12 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
             eval_state(p, d, F, wc, xi, u, grad ? dxi : NULL);
             if (grad)
                 for (int i = 0; i < d * F; ++i) g[i] = dxi[i] * 2.0 / h; /* physical gradient */
-            double flux[3][5];
+            double flux[3][6];
             for (int a = 0; a < d; ++a) {
-                or_euler_flux(d, pr->gamma, u, a, flux[a]);
-                if (pr->nu > 0.0 || pr->kappa > 0.0) {
-                    double fv[5];
-                    ns_flux(d, pr->gamma, pr->nu, pr->kappa, u, g, F, a, fv);
+                cons_flux(d, Fc, pr->gamma, u, a, flux[a]);
+                if (need_diff(pr)) {
+                    double fv[6];
+                    diff_flux(pr, u, g, F, a, fv);
                     for (int f = 0; f < Fc; ++f) flux[a][f] -= fv[f];
                 }
             }
@@ -671,7 +716,7 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
                 double tau = pr->f_tau * h / (p * cs);
                 src_alpha = pr->f_v * fmax(0.0, -div) + wig - u[Fc] / tau;
             }
-            double fsrc[5] = {0, 0, 0, 0, 0};
+            double fsrc[6] = {0, 0, 0, 0, 0, 0};
             if (pr->forcing) {
                 /* momentum source rho s, energy source rho s.v */
                 const double *sc = pr->forcing + c * 3L * M;
@@ -1035,10 +1080,11 @@ void or_step(const or_params *pr, double *w, double dt, double *R_state)
 #undef LIM
 }
 
-/* Conserved totals sum_K |K| w_0 per conserved field, Neumaier-compensated. */
+/* Conserved totals sum_K |K| w_0 per conserved field (tracer included),
+ * Neumaier-compensated. */
 void or_totals(const or_params *pr, const double *w, double *out)
 {
-    const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = d + 2, M = ipow(p, d);
+    const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = n_cons(pr), M = ipow(p, d);
     const long NC = n_cells(pr);
     double vol = pow(pr->h, d);
     for (int f = 0; f < Fc; ++f) {

@@ -2,7 +2,7 @@
  * dg_oracle.h -- interface of the plain FP64 CPU oracle (test infrastructure
  * only; see dg_oracle.c).  Host arrays only.  State layout:
  * w[cell][field][mode], cell = i + n0 (j + n1 k), mode = l_x + p (l_y + p l_z),
- * fields (rho, rho v_x, rho v_y[, rho v_z], e[, alpha]).
+ * fields (rho, rho v_x, rho v_y[, rho v_z], e[, c rho][, alpha]).
  */
 #ifndef DG_ORACLE_H
 #define DG_ORACLE_H
@@ -19,6 +19,8 @@ typedef struct {
     double cfl;
     const double *forcing; /* [cell][3][p^d] coefficients of s, or NULL */
     int limiter;       /* positivity limiter after every RK stage (Sec. 4.2) */
+    int tracer;        /* passive tracer field c rho after e (Sec. 3.4) */
+    double eta;        /* its diffusivity */
 } or_params;
 
 void or_legendre(int lmax, double x, double *Pt, double *dPt);

@@ -16,6 +16,7 @@ Workloads (shapes and value structure of the paper's problems):
   * ``kelvin_helmholtz`` 2D shear layer on [0,1]x[0,2] (stand-in for the
     Lecoanet et al. benchmark used in Sec. 6; its reference data is not used).
   * ``sod``            2D shock tube on [0,1]x[0,h*ny], (1,1) | (0.125,0.1).
+  * ``gaussian_pulse`` passive-tracer Gaussian at rest on [-0.5,0.5]^2 (periodic images).
   * ``turbulence``     3D periodic box, rho = 1, c_s = 1, random solenoidal
     velocity on 1 <= |k| <= 3 with amplitude ~ k^(-8/3), rms Mach 0.3, plus a
     solenoidal forcing field on the same band (Sec. 7 setup).
@@ -165,6 +166,30 @@ def sod(order, nx=1024, ny=128, device="cpu", with_alpha=True):
         return _conserved(rho, [z, z], P, gamma, extra)
 
     return project(fn, 2, (nx, ny), (0.0, 0.0), h, order, device)
+
+
+def gaussian_pulse(order, n=8, t=1.0, eta=1.0 / 128.0, device="cpu", gamma=1.4):
+    """Passive-tracer diffusion test (Sec. 5.2, eq. diffusion_spike): gas at
+    rest with rho = 1, P = 1 on the periodic square [-0.5, 0.5]^2 and the tracer
+    concentration c = c_b + sum_j c_g/(2 pi s^2) exp(-|x - j|^2 / (2 s^2)),
+    s^2 = 2 eta t, c_b = 1/10, c_g = 1, over the periodic images j (|j_a| <= 3).
+    Fields (rho, rho v_x, rho v_y, e, c rho)."""
+    cb, cg = 0.1, 1.0
+    s2 = 2.0 * eta * t
+
+    def fn(X):
+        x, y = X
+        c = cb * torch.ones_like(x)
+        for jx in range(-3, 4):
+            for jy in range(-3, 4):
+                r2 = (x - jx) ** 2 + (y - jy) ** 2
+                c = c + cg / (2.0 * math.pi * s2) * torch.exp(-r2 / (2.0 * s2))
+        one = torch.ones_like(x)
+        z = torch.zeros_like(x)
+        return _conserved(one, [z, z], one, gamma, (c,))
+
+    h = 1.0 / n
+    return project(fn, 2, (n, n), (-0.5, -0.5), h, order, device)
 
 
 def _solenoidal_modes(rng, kmax, slope):
