@@ -12,8 +12,9 @@
  *     1 <= p <= 8 (Sec. 2.3, 2.4).  Modes per field: p^dim (tensor set Q_n).
  *   - State layout (device, float64, C-contiguous): w[cell][field][mode],
  *     cell = i + n0 (j + n1 k), mode = l_x + p (l_y + p l_z); fields
- *     (rho, rho v_x, rho v_y[, rho v_z], e[, alpha]): dim + 2 conserved fields
- *     plus the artificial-viscosity field alpha when AV is enabled (Sec. 4.1).
+ *     (rho, rho v_x, rho v_y[, rho v_z], e[, c rho][, alpha]): dim + 2
+ *     conserved fields, the passive tracer c rho when enabled (Sec. 3.4), and
+ *     the artificial-viscosity field alpha when AV is enabled (Sec. 4.1).
  *     w_0 of each field is the cell mean (orthonormal basis, Sec. 2.2).
  *   - Every pointer argument named w, wdot, s_coeffs or R is a DEVICE pointer
  *     owned by the caller (e.g. a torch tensor), 8-byte aligned; w and wdot
@@ -93,7 +94,10 @@ typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_BULK = 1 } dg_precision;
  * face-kernel pencil, threads per volume / face block (multiples of 64,
  * at most 512).  Results do not depend on the tiles.  limiter = 1: the
  * positivity limiter of dg_limit acts on every state an RK stage writes
- * (default 0; not available for batched ensembles). */
+ * (default 0; not available for batched ensembles).  tracer = 1 adds the
+ * passive tracer c rho (Sec. 3.4 eq. passivetracer) as a conserved field
+ * after e: flux c rho v minus the diffusion eta rho grad c, eta =
+ * tracer_eta >= 0 (default off; not with AV, not for batched ensembles). */
 typedef struct {
     int precision;
     int basis;
@@ -103,6 +107,8 @@ typedef struct {
     int vol_threads;
     int face_threads;
     int limiter;
+    int tracer;
+    double tracer_eta;
 } dg_options;
 
 void dg_av_defaults(dg_av_params *av);
@@ -124,8 +130,11 @@ void dg_free(dg_ctx *ctx);
 
 /* Number of doubles of a state array: cells * fields * order^dim. */
 size_t dg_state_len(const dg_ctx *ctx);
-/* Number of fields per cell (dim + 2, + 1 with AV). */
+/* Number of fields per cell (dim + 2, + 1 with the tracer, + 1 with AV). */
 int dg_num_fields(const dg_ctx *ctx);
+/* Number of conserved fields (dim + 2, + 1 with the tracer): the values
+ * dg_conserved_totals returns. */
+int dg_num_conserved(const dg_ctx *ctx);
 
 /* Shape of the context (host pointers, any may be NULL): dimension, order p,
  * number of cells and fields per cell.  A state array holds
@@ -187,8 +196,8 @@ dg_status dg_max_dt(dg_ctx *ctx, const double *w, double *dt_out, double *cmax_o
  * the caller. */
 dg_status dg_max_dt_noalloc(dg_ctx *ctx, const double *w, double *out, void *stream);
 
-/* Conserved totals sum_K |K| w_0 per conserved field (dim + 2 values, host
- * pointer `out`), deterministic compensated FP64 sums.  The integral of each
+/* Conserved totals sum_K |K| w_0 per conserved field (dg_num_conserved
+ * values, host pointer `out`), deterministic compensated FP64 sums.  The integral of each
  * conserved density over the box (Sec. 2.1: w_0 is the cell mean of the
  * orthonormal expansion, so |K| w_0 is the cell's content); on periodic
  * boxes the scheme keeps these constant (Sec. 3, manifestly conservative

@@ -41,7 +41,8 @@ class dg_av_params(ctypes.Structure):
 class dg_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("basis", ctypes.c_int), ("cfl", ctypes.c_double),
                 ("cells_per_block", ctypes.c_int), ("faces_per_block", ctypes.c_int),
-                ("vol_threads", ctypes.c_int), ("face_threads", ctypes.c_int), ("limiter", ctypes.c_int)]
+                ("vol_threads", ctypes.c_int), ("face_threads", ctypes.c_int), ("limiter", ctypes.c_int),
+                ("tracer", ctypes.c_int), ("tracer_eta", ctypes.c_double)]
 
 
 _V = ctypes.c_void_p
@@ -56,6 +57,7 @@ _SIGS = {
     "dg_free": (None, [_V]),
     "dg_state_len": (ctypes.c_size_t, [_V]),
     "dg_num_fields": (ctypes.c_int, [_V]),
+    "dg_num_conserved": (ctypes.c_int, [_V]),
     "dg_shape": (ctypes.c_int, [_V, _I, _I, ctypes.POINTER(ctypes.c_longlong), _I]),
     "dg_rhs": (ctypes.c_int, [_V, _V, _V, _V]),
     "dg_step": (ctypes.c_int, [_V, _V, ctypes.c_double, _V]),
@@ -179,6 +181,10 @@ def dg_num_fields(ctx):
     return lib().dg_num_fields(ctx)
 
 
+def dg_num_conserved(ctx):
+    return lib().dg_num_conserved(ctx)
+
+
 def dg_shape(ctx):
     """(dim, order, ncells, nfields) of a context."""
     d, o, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -218,8 +224,8 @@ def dg_max_dt_noalloc(ctx, w, out, stream=None):
          "dg_max_dt_noalloc")
 
 
-def dg_conserved_totals(ctx, w, dim, stream=None):
-    out = (ctypes.c_double * (dim + 2))()
+def dg_conserved_totals(ctx, w, stream=None):
+    out = (ctypes.c_double * dg_num_conserved(ctx))()
     _chk(lib().dg_conserved_totals(ctx, _dptr(w, dg_state_len(ctx)), out, _stream(stream)),
          "dg_conserved_totals")
     return list(out)
@@ -350,11 +356,12 @@ class Solver:
     """One DG context on the current GPU.
 
     ``av``: None (off), True (paper defaults) or a dict overriding defaults.
+    ``tracer``/``eta``: the passive tracer field c rho and its diffusivity.
     ``precision``: "fp64" or "fp32" (FP32 bulk, FP64 state and RK)."""
 
     def __init__(self, dim, n, order, gamma, nu=0.0, kappa=0.0, lo=None, hi=None, bc=None, av=None,
                  precision="fp64", cfl=0.5, cells_per_block=0, faces_per_block=0, vol_threads=0,
-                 face_threads=0, limiter=False):
+                 face_threads=0, limiter=False, tracer=False, eta=0.0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the DG library runs on the GPU only")
         self.dim, self.order = dim, order
@@ -375,6 +382,8 @@ class Solver:
         opt.vol_threads = vol_threads
         opt.face_threads = face_threads
         opt.limiter = 1 if limiter else 0
+        opt.tracer = 1 if tracer else 0
+        opt.tracer_eta = eta
         self.ctx = dg_init(self.mesh, order, gamma, nu, kappa, avp, opt)
         self.nfields = dg_num_fields(self.ctx)
         self.ncells = 1
@@ -411,7 +420,7 @@ class Solver:
         dg_limit(self.ctx, w, stream)
 
     def totals(self, w, stream=None):
-        return dg_conserved_totals(self.ctx, w, self.dim, stream)
+        return dg_conserved_totals(self.ctx, w, stream)
 
     def set_forcing(self, s):
         self._forcing = s

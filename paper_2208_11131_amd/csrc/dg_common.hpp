@@ -6,7 +6,7 @@
 namespace dgk {
 
 constexpr int MAXP = 8;     // highest order (modes / Gauss points per axis)
-constexpr int MAXF = 9;     // stored fields (dim+2, +1 AV) plus dim forcing fields
+constexpr int MAXF = 9;     // stored fields (dim+2, +1 tracer or AV) plus dim forcing fields
 
 // Per-order 1D tables on the p Gauss-Legendre nodes x_j of [-1, 1]
 // (Sec. 2.3 scaled Legendre basis, Sec. 2.4 quadrature, Sec. 3.2 recovery).
@@ -33,15 +33,16 @@ struct Phys {
     double inv_fh;       // 1/(f h): d/dx = (1/(f h)) d/dxi* on the recovery domain
     double pref;         // 2^(1-d)/h: prefactor of volume and surface sums
     double half_h;       // h/2: converts a source projection to the common prefactor
-    int ns_on;           // nu > 0 or kappa > 0
+    int ns_on;           // nu > 0, kappa > 0 or a diffusing tracer (eta > 0)
     int av_on;           // AV field present
     double av_scale, f_v, sink;   // sink = p/(f_tau h): alpha/tau = alpha c_s sink
     double f_w, s_thr, alpha_max, eps_fac;   // s_thr = s_onset/p^2, eps_fac = h/p
     int order;           // p
+    double eta;          // passive-tracer diffusivity (Sec. 3.4)
 };
 
 // Mesh geometry.  Face space of direction a has nf[a] planes along a
-// (n[a] periodic, n[a]+1 outflow) and n[b] along the other axes.
+// (n[a] periodic, n[a]+1 with closed ends) and n[b] along the other axes.
 struct Geo {
     int n[3];
     int nf[3];

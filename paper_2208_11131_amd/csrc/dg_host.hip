@@ -296,7 +296,7 @@ __device__ __forceinline__ void nadd(double &s, double &c, double x)
 __global__ void totals_partial(const double *w, long long NC, int F, int NP, int Fc, double vol, int chunk,
                                double *part)
 {
-    __shared__ double ss[256 * 5], cc[256 * 5];
+    __shared__ double ss[256 * 6], cc[256 * 6];   // up to 6 conserved fields
     const long long c0 = (long long)blockIdx.x * chunk;
     const int tid = threadIdx.x;
     for (int f = 0; f < Fc; ++f) {
@@ -360,7 +360,7 @@ struct dg_ctx {
     double cfl;
     int device;
     bool grad;
-    int phys;    // 0 Euler, 1 Navier-Stokes, 2 artificial viscosity
+    int phys;    // 0 Euler, 1 Navier-Stokes, 2 artificial viscosity, 3 Navier-Stokes + tracer
     KernelSet ks, ks64;
     const void *vol_fixed[2];   // fixed-tile volume kernels (no forcing / forcing) for the tile in use, or null
     const void *face_fixed;     // fixed-tile face kernel for the tile in use, or null
@@ -697,6 +697,8 @@ void dg_options_defaults(dg_options *opt)
     opt->vol_threads = 0;
     opt->face_threads = 0;
     opt->limiter = 0;
+    opt->tracer = 0;
+    opt->tracer_eta = 0.0;
 }
 
 const char *dg_status_str(dg_status s)
@@ -731,6 +733,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     dg_options_defaults(&o);
     if (opt) o = *opt;
     if (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_BULK) return DG_EINVAL;
+    if (o.tracer && (!(o.tracer_eta >= 0.0) || !std::isfinite(o.tracer_eta))) return DG_EINVAL;
     if (o.basis != 0) return DG_EUNSUPPORTED;
     if (!(o.cfl > 0.0) || o.cells_per_block < 0 || o.faces_per_block < 0) return DG_EINVAL;
     if (o.vol_threads < 0 || o.vol_threads > 512 || o.vol_threads % 64 || o.face_threads < 0 ||
@@ -752,6 +755,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
             return DG_EINVAL;
     }
     const bool av_on = av && av->enabled;
+    if (av_on && o.tracer) return DG_EUNSUPPORTED;   // no AV variant carries the tracer
     if (av_on && (!(av->f_tau > 0.0) || !(av->alpha_max >= 0.0) || !(av->scale >= 0.0) || !(av->f_v >= 0.0) ||
                   !(av->f_w >= 0.0) || !(av->s_onset >= 0.0)))
         return DG_EINVAL;
@@ -767,7 +771,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     memset(c, 0, sizeof(*c));
     c->dim = d;
     c->P = order;
-    c->Fc = d + 2;
+    c->Fc = d + 2 + (o.tracer ? 1 : 0);
     c->F = c->Fc + (av_on ? 1 : 0);
     c->NP = 1;
     for (int a = 0; a < d; ++a) c->NP *= order;
@@ -811,7 +815,8 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     ph.inv_fh = 1.0 / (fr * h);
     ph.pref = std::pow(2.0, 1 - d) / h;
     ph.half_h = 0.5 * h;
-    ph.ns_on = (nu > 0.0 || kappa > 0.0) ? 1 : 0;
+    ph.eta = o.tracer ? o.tracer_eta : 0.0;
+    ph.ns_on = (nu > 0.0 || kappa > 0.0 || ph.eta > 0.0) ? 1 : 0;
     ph.av_on = av_on ? 1 : 0;
     if (av_on) {
         ph.av_scale = av->scale;
@@ -823,7 +828,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         ph.eps_fac = h / order;
     }
     c->grad = ph.ns_on || ph.av_on;
-    c->phys = ph.av_on ? 2 : (ph.ns_on ? 1 : 0);
+    c->phys = ph.av_on ? 2 : (o.tracer ? 3 : (ph.ns_on ? 1 : 0));
     get_kernels(d, c->precision, order, c->phys, &c->ks);
     get_kernels(d, DG_PREC_FP64, order, c->phys, &c->ks64);
     if (!c->ks.vol || !c->ks.face || !c->ks64.cfl) {
@@ -1014,6 +1019,8 @@ dg_status dg_timing_read(dg_ctx *c, double *face_ms, long long *face_n, double *
 size_t dg_state_len(const dg_ctx *c) { return c ? (size_t)c->ncells * c->F * c->NP : 0; }
 
 int dg_num_fields(const dg_ctx *c) { return c ? c->F : 0; }
+
+int dg_num_conserved(const dg_ctx *c) { return c ? c->Fc : 0; }
 
 dg_status dg_shape(const dg_ctx *c, int *dim, int *order, long long *ncells, int *nfields)
 {
@@ -1338,7 +1345,7 @@ static dg_status batch_init_impl(int nbox, const dg_mesh *meshes, const int *ord
     *out = nullptr;
     if (nbox < 1 || !meshes || !orders) return DG_EINVAL;
     if (av && av->enabled) return DG_EUNSUPPORTED;
-    if (opt && opt->limiter) return DG_EUNSUPPORTED;
+    if (opt && (opt->limiter || opt->tracer)) return DG_EUNSUPPORTED;
     for (int i = 0; i < nbox; ++i)
         if (meshes[i].dim != meshes[0].dim) return DG_EINVAL;
     dg_batch *b = new (std::nothrow) dg_batch;

@@ -1,5 +1,6 @@
 // Kernel instantiations: dim = 3, bulk precision float, orders 1..8,
-// physics variants Euler / Navier-Stokes / artificial viscosity.
+// physics variants Euler / Navier-Stokes / artificial viscosity /
+// Navier-Stokes with the passive tracer.
 #include "dg_kernels.hpp"
 #include "dg_registry.hpp"
 
@@ -29,8 +30,10 @@ void pick(int ph, KernelSet *k)
         fill<P, 0>(k);
     else if (ph == 1)
         fill<P, 1>(k);
-    else
+    else if (ph == 2)
         fill<P, 2>(k);
+    else
+        fill<P, 3>(k);
 }
 }  // namespace
 

@@ -246,12 +246,17 @@ __device__ __forceinline__ void dt_lift_pass(const T *__restrict__ in, T *__rest
 }
 
 // Fields per physics variant: PH = 0 Euler, 1 Navier-Stokes, 2 artificial
-// viscosity (alpha field; Navier-Stokes terms switched at run time).
+// viscosity (alpha field; Navier-Stokes terms switched at run time),
+// 3 Navier-Stokes with the passive tracer c rho (Sec. 3.4).  Fc conserved
+// fields carry face fluxes: the D + 2 hydro fields and the tracer.
 template <int D, int PH>
 struct Fld {
-    static constexpr int Fc = D + 2;
-    static constexpr int F = D + 2 + (PH == 2 ? 1 : 0);
+    static constexpr int NH = D + 2;
+    static constexpr bool TR = PH == 3;
+    static constexpr int Fc = NH + (TR ? 1 : 0);
+    static constexpr int F = Fc + (PH == 2 ? 1 : 0);
     static constexpr bool GRAD = PH > 0;
+    static constexpr bool NS = PH == 1 || PH == 3;   // Navier-Stokes terms compiled in
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
@@ -299,8 +304,10 @@ __device__ __forceinline__ void euler_flux(const T *u, const Prim<D, T> &s, int 
     f[D + 1] = (u[D + 1] + s.p) * s.v[a];
 }
 
-// HLLC flux (Toro ch. 10) with Davis wave-speed bounds.
-template <int D, typename T>
+// HLLC flux (Toro ch. 10) with Davis wave-speed bounds, for NC conserved
+// fields: the hydro fields and (NC = D + 3) a passive scalar c rho, whose
+// flux is c rho v_a and whose star state is c_K times the star density.
+template <int D, typename T, int NC = D + 2>
 __device__ __forceinline__ void hllc(const T *uL, const T *uR, int a, T gamma, T *F)
 {
     const Prim<D, T> L = primitives<D, T>(uL, gamma);
@@ -311,10 +318,12 @@ __device__ __forceinline__ void hllc(const T *uL, const T *uR, int a, T gamma, T
     const T SR = fmax(unL + cL, unR + cR);
     if (T(0) <= SL) {
         euler_flux<D, T>(uL, L, a, F);
+        if (NC > D + 2) F[D + 2] = uL[D + 2] * L.v[a];
         return;
     }
     if (SR <= T(0)) {
         euler_flux<D, T>(uR, R, a, F);
+        if (NC > D + 2) F[D + 2] = uR[D + 2] * R.v[a];
         return;
     }
     const T Ss = (R.p - L.p + L.rho * unL * (SL - unL) - R.rho * unR * (SR - unR)) /
@@ -325,14 +334,16 @@ __device__ __forceinline__ void hllc(const T *uL, const T *uR, int a, T gamma, T
     const T S = left ? SL : SR;
     const T un = K.v[a];
     euler_flux<D, T>(u, K, a, F);
+    if (NC > D + 2) F[D + 2] = u[D + 2] * K.v[a];
     const T fac = K.rho * (S - un) / (S - Ss);
-    T us[D + 2];
+    T us[NC];
     us[0] = fac;
 #pragma unroll
     for (int i = 0; i < D; ++i) us[1 + i] = (i == a) ? fac * Ss : fac * K.v[i];
     us[D + 1] = fac * (u[D + 1] * K.ir + (Ss - un) * (Ss + K.p / (K.rho * (S - un))));
+    if (NC > D + 2) us[D + 2] = fac * (u[D + 2] * K.ir);
 #pragma unroll
-    for (int k = 0; k < D + 2; ++k) F[k] += S * (us[k] - u[k]);
+    for (int k = 0; k < NC; ++k) F[k] += S * (us[k] - u[k]);
 }
 
 // Navier-Stokes flux (added with a minus sign to the Euler flux), Sec. 3.3:
@@ -602,29 +613,31 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         }
         const Prim<D, T> s = primitives<D, T>(ut, gamma);
 #pragma unroll
-        for (int f = 0; f < D + 2; ++f) vis[f] = T(0);
-        if (PH == 1 || ph.ns_on) {
+        for (int f = 0; f < Fc; ++f) vis[f] = T(0);
+        if (Fld<D, PH>::NS || ph.ns_on) {
             T fv[D + 2];
             const NsGrad<D, T> ng = ns_grad<D, T>(ut, s, g);
             ns_flux<D, T>(s, ng, AX, gamma, (T)ph.nu, (T)ph.kappa, fv);
 #pragma unroll
             for (int f = 0; f < D + 2; ++f) vis[f] = fv[f];
+            // tracer diffusion eta rho d_a c = eta (d_a(c rho) - c d_a rho)
+            if (Fld<D, PH>::TR) vis[D + 2] = (T)ph.eta * (g[AX][D + 2] - ut[D + 2] * s.ir * g[AX][0]);
         }
         if (PH == 2) {
             const T cs = sqrt(gamma * s.p * s.ir);
-            const T eps = (T)ph.av_scale * clamp_alpha(ut[D + 2], (T)ph.alpha_max) * cs * (T)ph.eps_fac;
+            const T eps = (T)ph.av_scale * clamp_alpha(ut[Fc], (T)ph.alpha_max) * cs * (T)ph.eps_fac;
 #pragma unroll
-            for (int f = 0; f < D + 2; ++f) vis[f] += eps * g[AX][f];
+            for (int f = 0; f < Fc; ++f) vis[f] += eps * g[AX][f];
         }
     };
     auto riemann = [&](int c, int kp, T *Fh) {
-        T uL[D + 2], uR[D + 2];
+        T uL[Fc], uR[Fc];
 #pragma unroll
-        for (int f = 0; f < D + 2; ++f) {
+        for (int f = 0; f < Fc; ++f) {
             uL[f] = tLp[(c * F + f) * NAF + kp];
             uR[f] = tRp[(c * F + f) * NAF + kp];
         }
-        hllc<D, T>(uL, uR, AX, gamma, Fh);
+        hllc<D, T, Fc>(uL, uR, AX, gamma, Fh);
     };
     auto store = [&](int c, int k, const T *Fh) {
         T gk = tb.g[k % P];
@@ -636,19 +649,19 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
         const long long fi = cf[0] + nd0 * (cf[1] + nd1 * cf[2]);
         T *dst = fb + fi * (long long)(Fc * K) + k;
 #pragma unroll
-        for (int f = 0; f < D + 2; ++f) dst[f * K] = gk * Fh[f];
+        for (int f = 0; f < Fc; ++f) dst[f * K] = gk * Fh[f];
     };
     for (int q = tid; q < C * K; q += nt) {
         const int c = q / K, k = q - c * K;
         if (c >= nface) continue;
         const int kp = ppos<P, PP>(k);
-        T Fh[D + 2];
+        T Fh[Fc];
         riemann(c, kp, Fh);
         if (GRAD) {
-            T vis[D + 2];
+            T vis[Fc];
             viscous(c, kp, vis);
 #pragma unroll
-            for (int f = 0; f < D + 2; ++f) Fh[f] -= vis[f];
+            for (int f = 0; f < Fc; ++f) Fh[f] -= vis[f];
         }
         store(c, k, Fh);
     }
@@ -831,9 +844,9 @@ __host__ __device__ constexpr size_t vol_hdr_bytes(int C)
 }
 
 template <int D, int P>
-__host__ __device__ constexpr size_t vol_m0_bytes(int C)
+__host__ __device__ constexpr size_t vol_m0_bytes(int C, int Fc)
 {
-    return (size_t)(D + 2) * C * ipow(P, D - 1) * sizeof(double);
+    return (size_t)Fc * C * ipow(P, D - 1) * sizeof(double);
 }
 
 // CC, NTC, FO: cells per block, threads per block and forcing (0 off, 1 on)
@@ -868,7 +881,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     double *cmean = cellv + C;                // [C][D+2]: new cell means (checks)
     int *blkflag = (int *)(cmean + C * (D + 2));
     double *m0s = (double *)(smem + vol_hdr_bytes<D>(C));   // [Fc][C][K] FP64 surface sums
-    T *Ub = (T *)(smem + vol_hdr_bytes<D>(C) + vol_m0_bytes<D, P>(C));
+    T *Ub = (T *)(smem + vol_hdr_bytes<D>(C) + vol_m0_bytes<D, P>(C, Fc));
     T *G = Ub + Fx * CNP;
     T *X0 = (D == 3) ? G : Ub;     // the last of the D passes lands in Ub
     T *X1 = (D == 3) ? Ub : G;
@@ -1030,26 +1043,28 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         if (GRAD) ng = ns_grad<D, T>(u, s, g);
 #pragma unroll
         for (int b = 0; b < D; ++b) {
-            T fl[D + 2];
+            T fl[Fc];
             euler_flux<D, T>(u, s, b, fl);
-            if (PH == 1 || (PH == 2 && ph.ns_on)) {
+            if (Fld<D, PH>::TR) fl[D + 2] = u[D + 2] * s.v[b];
+            if (Fld<D, PH>::NS || (PH == 2 && ph.ns_on)) {
                 T fv[D + 2];
                 ns_flux<D, T>(s, ng, b, gamma, (T)ph.nu, (T)ph.kappa, fv);
 #pragma unroll
                 for (int f = 0; f < D + 2; ++f) fl[f] -= fv[f];
+                if (Fld<D, PH>::TR) fl[D + 2] -= (T)ph.eta * (g[b][D + 2] - u[D + 2] * s.ir * g[b][0]);
             }
             if (PH == 2) {
 #pragma unroll
-                for (int f = 0; f < D + 2; ++f) fl[f] -= eps * g[b][f];
+                for (int f = 0; f < Fc; ++f) fl[f] -= eps * g[b][f];
             }
 #pragma unroll
-            for (int f = 0; f < D + 2; ++f) G[(b * F + f) * CNP + q] = wq * fl[f];
+            for (int f = 0; f < Fc; ++f) G[(b * F + f) * CNP + q] = wq * fl[f];
         }
         // sources, scaled to the common prefactor: Q = (h/2) w_j src
         const T hw = (T)ph.half_h * wq;
-        T src[D + 2];
+        T src[Fc];
 #pragma unroll
-        for (int f = 0; f < D + 2; ++f) src[f] = T(0);
+        for (int f = 0; f < Fc; ++f) src[f] = T(0);
         if (forced) {
             T sv = T(0);
 #pragma unroll
@@ -1060,7 +1075,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
             src[D + 1] = sv;
         }
 #pragma unroll
-        for (int f = 0; f < D + 2; ++f) U[f * CNP + q] = hw * src[f];
+        for (int f = 0; f < Fc; ++f) U[f * CNP + q] = hw * src[f];
         if (PH == 2) {
             const T asrc = (T)ph.f_v * fmax(T(0), -ng.div) + (T)cellv[cq] - u[Fc] * cs * (T)ph.sink;
             U[Fc * CNP + q] = hw * asrc;
@@ -1249,7 +1264,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         // term vanishes (Pt_0' = 0), so its RHS is the FP64 sum of the face
         // fluxes over the cell's faces (single-valued fluxes: the totals are
         // conserved to FP64 rounding also with an FP32 bulk)
-        const bool m0 = t == 0 && f < Fc && (f == 0 || !forced);
+        const bool m0 = t == 0 && f < Fc && (f == 0 || f == D + 2 || !forced);   // forcing: momentum, energy
         double y0 = (double)y[0];
         if (m0) {
             y0 = 0.0;
@@ -1413,7 +1428,8 @@ size_t vol_lds_bytes(int C, int Fx)
 {
     constexpr int NP = Pad<P>::PP * ipow(P, D - 1);   // padded per-cell array
     constexpr int F = Fld<D, PH>::F;
-    return vol_hdr_bytes<D>(C) + vol_m0_bytes<D, P>(C) + sizeof(T) * ((size_t)C * Fx * NP + (size_t)C * D * F * NP);
+    return vol_hdr_bytes<D>(C) + vol_m0_bytes<D, P>(C, Fld<D, PH>::Fc) +
+           sizeof(T) * ((size_t)C * Fx * NP + (size_t)C * D * F * NP);
 }
 
 // ---------------------------------------------------------------------------
