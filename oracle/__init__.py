@@ -71,6 +71,10 @@ def _load():
             "or_step": (None, [P, _D, ctypes.c_double, _D]),
             "or_totals": (None, [P, _D, _D]),
             "or_limit": (ctypes.c_long, [P, _D]),
+            "or_forcing_modes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+            "or_ou_update": (None, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+            "or_forcing_project": (None, [P, _D, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D]),
             "or_num_threads": (ctypes.c_int, []),
             "or_set_num_threads": (None, [ctypes.c_int]),
         }
@@ -209,6 +213,40 @@ class Problem:
         wR = np.ascontiguousarray(wR, dtype=np.float64)
         lib.or_recover_face(ctypes.byref(self.p), _ptr(wL), _ptr(wR), axis, _ptr(ut), _ptr(gt))
         return ut, gt
+
+
+def forcing_modes(dim, kmax):
+    """Wave vectors of the driving field, (n, 3) int array (Sec. 7.1)."""
+    lib = _load()
+    n = lib.or_forcing_modes(dim, kmax, None)
+    kv = np.zeros((n, 3), dtype=np.int32)
+    lib.or_forcing_modes(dim, kmax, kv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return kv
+
+
+def ou_update(dim, kv, amp, noise, dt, t_corr, sigma0):
+    """One Ornstein-Uhlenbeck step of the amplitudes (nm, 3, 2); returns a copy."""
+    lib = _load()
+    kv = np.ascontiguousarray(kv, dtype=np.int32)
+    a = np.array(amp, dtype=np.float64, order="C", copy=True)
+    nz = np.ascontiguousarray(noise, dtype=np.float64)
+    assert a.shape == (len(kv), 3, 2) and nz.shape == a.shape
+    lib.or_ou_update(dim, len(kv), kv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(a), _ptr(nz),
+                     float(dt), float(t_corr), float(sigma0))
+    return a
+
+
+def forcing_project(prob, lo, kv, amp):
+    """DG coefficients (ncells, 3, p^d) of the driving field of the amplitudes."""
+    lib = _load()
+    kv = np.ascontiguousarray(kv, dtype=np.int32)
+    a = np.ascontiguousarray(amp, dtype=np.float64)
+    lo3 = np.zeros(3)
+    lo3[:len(lo)] = lo
+    out = np.zeros((prob.ncells, 3, prob.nmodes))
+    lib.or_forcing_project(ctypes.byref(prob.p), _ptr(lo3), len(kv), kv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                           _ptr(a), _ptr(out))
+    return out
 
 
 def legendre(lmax, x):

@@ -844,6 +844,122 @@ void or_rhs_abs(const or_params *pr, const double *w, const double *R_prev, long
 }
 
 /* ------------------------------------------------------------------------- */
+/* Driving field (Sec. 7.1): Ornstein-Uhlenbeck modes, projection on the basis */
+/* ------------------------------------------------------------------------- */
+
+/* Wave vectors k (integer components, unit box) with 1 <= |k|^2 <= kmax^2,
+ * one of each pair +-k (the one whose first non-zero component is positive),
+ * ordered by k_x, then k_y, then k_z ascending; k_z = 0 in 2D.  Writes kv[3 i]
+ * (if not NULL) and returns the count. */
+int or_forcing_modes(int dim, int kmax, int *kv)
+{
+    int n = 0;
+    const int kzm = dim == 3 ? kmax : 0;
+    for (int kx = -kmax; kx <= kmax; ++kx)
+        for (int ky = -kmax; ky <= kmax; ++ky)
+            for (int kz = -kzm; kz <= kzm; ++kz) {
+                int k2 = kx * kx + ky * ky + kz * kz;
+                if (k2 < 1 || k2 > kmax * kmax) continue;
+                int first = kx != 0 ? kx : (ky != 0 ? ky : kz);
+                if (first < 0) continue;
+                if (kv) {
+                    kv[3 * n] = kx;
+                    kv[3 * n + 1] = ky;
+                    kv[3 * n + 2] = kz;
+                }
+                ++n;
+            }
+    return n;
+}
+
+/* One Ornstein-Uhlenbeck update of the complex mode amplitudes amp[i][c][re,im]
+ * over a time dt with correlation time t_corr: every component becomes
+ * f a + sigma_k sqrt(1 - f^2) (xi_re + i xi_im) / sqrt(2), f = exp(-dt/t_corr),
+ * sigma_k = sigma0 |k|^(-5/3) (the k^(-5/3) amplitude scaling of Sec. 7.1),
+ * xi = noise[i][c][re,im] standard normal draws supplied by the caller; then
+ * the compressive part is removed, a -= k (k.a) / |k|^2 (the solenoidal
+ * projection of Sec. 7.1).  dt = +inf draws from the stationary law. */
+void or_ou_update(int dim, int nm, const int *kv, double *amp, const double *noise, double dt, double t_corr,
+                  double sigma0)
+{
+    const double f = exp(-dt / t_corr);
+    const double g = sqrt(1.0 - f * f);
+    for (int i = 0; i < nm; ++i) {
+        double k[3] = {kv[3 * i], kv[3 * i + 1], kv[3 * i + 2]};
+        double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        double sig = sigma0 * pow(k2, -5.0 / 6.0);
+        for (int c = 0; c < dim; ++c)
+            for (int r = 0; r < 2; ++r) {
+                double *a = amp + (i * 3 + c) * 2 + r;
+                *a = f * (*a) + sig * g * noise[(i * 3 + c) * 2 + r] / sqrt(2.0);
+            }
+        for (int r = 0; r < 2; ++r) {
+            double kd = 0.0;
+            for (int c = 0; c < dim; ++c) kd += k[c] * amp[(i * 3 + c) * 2 + r];
+            for (int c = 0; c < dim; ++c) amp[(i * 3 + c) * 2 + r] -= k[c] * kd / k2;
+        }
+    }
+}
+
+/* Driving field s(x) = sum_i 2 Re(a_i exp(2 pi i k_i . x)) at a point. */
+static void forcing_value(int dim, int nm, const int *kv, const double *amp, const double *x, double *sv)
+{
+    for (int c = 0; c < dim; ++c) sv[c] = 0.0;
+    for (int i = 0; i < nm; ++i) {
+        double ph = 0.0;
+        for (int a = 0; a < dim; ++a) ph += kv[3 * i + a] * x[a];
+        double cr = cos(2.0 * M_PI * ph), ci = sin(2.0 * M_PI * ph);
+        for (int c = 0; c < dim; ++c)
+            sv[c] += 2.0 * (amp[(i * 3 + c) * 2] * cr - amp[(i * 3 + c) * 2 + 1] * ci);
+    }
+}
+
+/* DG coefficients of the driving field, s_l^K = (1/|K|) int_K s phi_l
+ * (Sec. 2.2 eq. weights_equation), by Gauss quadrature with 16 points per
+ * axis (exact to rounding for these band-limited fields).  lo: lower corner of
+ * the box.  s[(cell * 3 + c) * p^d + l] (3 components per cell, the unused
+ * third one 0 in 2D), the layout the RHS reads. */
+void or_forcing_project(const or_params *pr, const double *lo, int nm, const int *kv, const double *amp,
+                        double *s)
+{
+    const int p = pr->order, d = pr->dim, M = ipow(p, d);
+    const long NC = n_cells(pr);
+    const int nq = 16;
+    double xq[16], wq[16];
+    or_gauss(nq, xq, wq);
+    const int NQ = ipow(nq, d);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long c = 0; c < NC; ++c) {
+        int ijk[3];
+        cell_coords(pr, c, ijk);
+        double *sc = s + c * 3L * M;
+        for (int i = 0; i < 3 * M; ++i) sc[i] = 0.0;
+        for (int j = 0; j < NQ; ++j) {
+            int jj = j;
+            double xi[3] = {0, 0, 0}, x[3] = {0, 0, 0}, wt = 1.0;
+            for (int a = 0; a < d; ++a) {
+                int q = jj % nq;
+                jj /= nq;
+                xi[a] = xq[q];
+                wt *= 0.5 * wq[q];
+                x[a] = lo[a] + (ijk[a] + 0.5 + 0.5 * xq[q]) * pr->h;
+            }
+            double sv[3];
+            forcing_value(d, nm, kv, amp, x, sv);
+            double Pt[3][OR_MAXP + 2];
+            for (int a = 0; a < d; ++a) or_legendre(p - 1, xi[a], Pt[a], NULL);
+            for (int m = 0; m < M; ++m) {
+                int l[3];
+                mode_degrees(p, d, m, l);
+                double phi = 1.0;
+                for (int a = 0; a < d; ++a) phi *= Pt[a][l[a]];
+                for (int cc = 0; cc < d; ++cc) sc[cc * M + m] += wt * phi * sv[cc];
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Positivity limiter (Sec. 4.2)                                             */
 /* ------------------------------------------------------------------------- */
 

@@ -41,6 +41,11 @@ int or_rk_stages(int order);
 void or_step(const or_params *pr, double *w, double dt, double *R_state);
 void or_totals(const or_params *pr, const double *w, double *out);
 long or_limit(const or_params *pr, double *w);
+int or_forcing_modes(int dim, int kmax, int *kv);
+void or_ou_update(int dim, int nm, const int *kv, double *amp, const double *noise, double dt, double t_corr,
+                  double sigma0);
+void or_forcing_project(const or_params *pr, const double *lo, int nm, const int *kv, const double *amp,
+                        double *s);
 int or_num_threads(void);
 void or_set_num_threads(int n);
 
