@@ -9,7 +9,10 @@ before the timed region; nothing leaves the device inside it.
 Headline workload: the 3D driven-turbulence box, 128^3 cells on the periodic
 unit cube, order p = 4 (64 modes x 5 fields per cell, 671M DOFs), Navier-
 Stokes with nu = kappa = 2e-5 and the solenoidal driving source, gamma =
-1.0001, FP64 (the largest single-GPU configuration).  Metric: DOF-updates per
+1.0001, FP64 (the largest single-GPU configuration).  The driving field is an
+Ornstein-Uhlenbeck process on the modes 1 <= |k| <= 3 (seeded draws): every
+ceil(0.01 / dt) steps, inside the timed region, its amplitudes are updated on
+the host and re-projected on the device (dg_forcing_update / _project).  Metric: DOF-updates per
 second per RK stage, (cells x modes x fields x stages) / time; the median of
 five repeats of --steps timed steps after --warmup untimed ones.
 
@@ -133,12 +136,27 @@ def make_workload(name, order, device, precision):
         return s, w, None, desc, dict(dim=2, ns=True, av=False)
     if name == "turb":
         n = 128
-        w, f = W.turbulence(order, n, device=device)
+        w, _ = W.turbulence(order, n, device=device)
         s = dg.Solver(3, (n, n, n), order, 1.0001, nu=2e-5, kappa=2e-5, precision=precision, cfl=0.5)
+        drv = dg.Driving(3, (n, n, n), order, kmax=3, t_corr=1.0, sigma0=0.5)
+        f = torch.empty(s.ncells * 3 * s.nmodes, dtype=torch.float64, device=device)
+        noise = W.ou_noise(drv.nm, 1024, seed=2208)
+        drv.update(noise[0], math.inf)                       # stationary start
+        drv.project(f)
         s.set_forcing(f)
+        dt0 = s.max_dt(w)[0]
+        every = max(1, int(math.ceil(0.01 / dt0)))            # OU update interval 0.01
+        state = {"k": 1}
+
+        def refresh(step):
+            if step % every == 0:
+                drv.update(noise[state["k"] % len(noise)], every * dt0)
+                state["k"] += 1
+                drv.project(f)
         desc = {"workload": "driven_turbulence_3d", "cells": [n, n, n], "order": order, "fields": 5,
-                "physics": "navier_stokes nu=kappa=2e-5 + forcing", "gamma": 1.0001}
-        return s, w, f, desc, dict(dim=3, ns=True, av=False)
+                "physics": "navier_stokes nu=kappa=2e-5 + OU driving", "gamma": 1.0001,
+                "driving": "OU modes 1<=|k|<=3, update + projection every %d steps" % every}
+        return s, w, f, desc, dict(dim=3, ns=True, av=False, refresh=refresh, keep=drv)
     if name == "sod":
         nx, ny = 1024, 128
         w = W.sod(order, nx, ny, device=device)
@@ -166,8 +184,11 @@ def measure(name, order, precision, steps, warmup, repeats=1, device="cuda"):
     sampled = set(range(steps - 1, -1, -EVENT_EVERY))
     # warm-up; its last len(sampled) steps record per-kernel events, so the
     # event pool is filled before the timed region (read and dropped below)
+    refresh = phys.get("refresh")
     for i in range(warmup):
         dg.dg_timing_enable(s.ctx, i >= warmup - len(sampled))
+        if refresh:
+            refresh(i)
         s.step_cfl(w)
     dg.dg_timing_enable(s.ctx, False)
     torch.cuda.synchronize()
@@ -188,6 +209,8 @@ def measure(name, order, precision, steps, warmup, repeats=1, device="cuda"):
         e0.record(stream)
         for i in range(steps):
             dg.dg_timing_enable(s.ctx, i in sampled)
+            if refresh:
+                refresh(warmup + i)
             s.step_cfl(w)
         dg.dg_timing_enable(s.ctx, False)
         e1.record(stream)

@@ -211,6 +211,46 @@ dg_status dg_conserved_totals(dg_ctx *ctx, const double *w, double *out, void *s
  * removes the forcing. */
 dg_status dg_set_forcing(dg_ctx *ctx, const double *s_coeffs);
 
+/* ---------------------------------------------------------------------------
+ * Driving field (Sec. 7.1 Driving): s(x) = sum_k 2 Re(a_k exp(2 pi i k.x)) over
+ * the integer wave vectors 1 <= |k|^2 <= k_max^2 (one of each pair +-k: the
+ * one whose first non-zero component is positive; ordered by k_x, then k_y,
+ * then k_z ascending; k_z = 0 in 2D), with complex amplitude vectors a_k that
+ * follow an Ornstein-Uhlenbeck process (correlation time t_corr, stationary
+ * standard deviation sigma0 |k|^(-5/3) per component, the k^(-5/3) scaling of
+ * Sec. 7.1) and are kept solenoidal, a_k -= k (k.a_k) / |k|^2 (the Helmholtz
+ * projection of Sec. 7.1).  The update runs on the host in FP64; the random
+ * draws are the caller's.  The projection on the DG basis runs on the device
+ * and produces the array dg_set_forcing takes.
+ * ------------------------------------------------------------------------- */
+typedef struct dg_forcing dg_forcing;
+
+/* Driving field on the box of `mesh` (periodic unit-length box expected) for
+ * order p; 1 <= kmax <= 4, t_corr > 0, sigma0 >= 0.  Amplitudes start at 0.
+ * Host allocation only (the device table is allocated by the first
+ * dg_forcing_project).  *out = NULL on error. */
+dg_status dg_forcing_init(const dg_mesh *mesh, int order, int kmax, double t_corr, double sigma0,
+                          dg_forcing **out);
+void dg_forcing_free(dg_forcing *f);
+/* Number of modes (one per +-k pair), and their wave vectors (host int[nm][3]). */
+int dg_forcing_num_modes(const dg_forcing *f);
+dg_status dg_forcing_modes(const dg_forcing *f, int *kv);
+/* Amplitudes, host double[nm][3][2] (re, im per component; the third
+ * component unused in 2D). */
+dg_status dg_forcing_get_amplitudes(const dg_forcing *f, double *amp);
+dg_status dg_forcing_set_amplitudes(dg_forcing *f, const double *amp);
+/* One OU step over dt > 0: every component becomes
+ * e^{-dt/t_corr} a + sigma_k sqrt(1 - e^{-2 dt/t_corr}) (xi_re + i xi_im)/sqrt(2)
+ * with the caller's standard normal draws noise[nm][3][2] (host), then the
+ * solenoidal projection.  dt = +inf draws from the stationary law.  Host only. */
+dg_status dg_forcing_update(dg_forcing *f, const double *noise, double dt);
+/* DG coefficients of s on every cell, s_coeffs (device, caller-owned,
+ * [cell][dim][p^dim] doubles): (1/|K|) int_K s phi_l, each mode's cell
+ * integral factorised into per-axis factors (1/2) int exp(i pi k_a h xi)
+ * Pt_l(xi) dxi tabulated on the host.  Copies the amplitudes to the device
+ * (synchronising `stream`), then enqueues one kernel. */
+dg_status dg_forcing_project(dg_forcing *f, double *s_coeffs, void *stream);
+
 /* Per-cell d ln S / dt used by the wiggle source (Sec. 4.1): copy from /
  * to a caller device array of ncells doubles (checkpointing, tests). */
 dg_status dg_set_sensor_rate(dg_ctx *ctx, const double *R, void *stream);

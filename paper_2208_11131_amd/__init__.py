@@ -83,6 +83,15 @@ _SIGS = {
     "dg_batch_dt": (ctypes.c_int, [_V, _D, _V]),
     "dg_batch_box": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(_V)]),
     "dg_batch_size": (ctypes.c_int, [_V]),
+    "dg_forcing_init": (ctypes.c_int, [ctypes.POINTER(dg_mesh), ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.POINTER(_V)]),
+    "dg_forcing_free": (None, [_V]),
+    "dg_forcing_num_modes": (ctypes.c_int, [_V]),
+    "dg_forcing_modes": (ctypes.c_int, [_V, _I]),
+    "dg_forcing_get_amplitudes": (ctypes.c_int, [_V, _D]),
+    "dg_forcing_set_amplitudes": (ctypes.c_int, [_V, _D]),
+    "dg_forcing_update": (ctypes.c_int, [_V, _D, ctypes.c_double]),
+    "dg_forcing_project": (ctypes.c_int, [_V, _V, _V]),
     "dg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
 }
 EXPORTS = tuple(_SIGS)
@@ -346,6 +355,98 @@ class Batch:
 
     def box_check(self, i, stream=None):
         return dg_check(dg_batch_box(self.b, i), stream)
+
+
+def dg_forcing_init(mesh, order, kmax, t_corr, sigma0):
+    f = _V()
+    _chk(lib().dg_forcing_init(ctypes.byref(mesh), order, kmax, t_corr, sigma0, ctypes.byref(f)), "dg_forcing_init")
+    return f
+
+
+def dg_forcing_free(f):
+    lib().dg_forcing_free(f)
+
+
+def dg_forcing_num_modes(f):
+    return lib().dg_forcing_num_modes(f)
+
+
+def dg_forcing_modes(f):
+    import numpy as np
+    kv = np.zeros((dg_forcing_num_modes(f), 3), dtype=np.int32)
+    _chk(lib().dg_forcing_modes(f, kv.ctypes.data_as(_I)), "dg_forcing_modes")
+    return kv
+
+
+def dg_forcing_get_amplitudes(f):
+    import numpy as np
+    a = np.zeros((dg_forcing_num_modes(f), 3, 2))
+    _chk(lib().dg_forcing_get_amplitudes(f, a.ctypes.data_as(_D)), "dg_forcing_get_amplitudes")
+    return a
+
+
+def _host_modes_array(f, a, what):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != (dg_forcing_num_modes(f), 3, 2):
+        raise ValueError("%s: expected shape %s, got %s" % (what, (dg_forcing_num_modes(f), 3, 2), a.shape))
+    return a
+
+
+def dg_forcing_set_amplitudes(f, a):
+    a = _host_modes_array(f, a, "dg_forcing_set_amplitudes")
+    _chk(lib().dg_forcing_set_amplitudes(f, a.ctypes.data_as(_D)), "dg_forcing_set_amplitudes")
+
+
+def dg_forcing_update(f, noise, dt):
+    z = _host_modes_array(f, noise, "dg_forcing_update")
+    _chk(lib().dg_forcing_update(f, z.ctypes.data_as(_D), float(dt)), "dg_forcing_update")
+
+
+def dg_forcing_project(f, s, stream=None):
+    _chk(lib().dg_forcing_project(f, _dptr(s), _stream(stream)), "dg_forcing_project")
+
+
+class Driving:
+    """Ornstein-Uhlenbeck driving field of one box (one dg_forcing)."""
+
+    def __init__(self, dim, n, order, kmax=3, t_corr=1.0, sigma0=1.0, lo=None, hi=None):
+        self.dim, self.order = dim, order
+        if hi is None:
+            hi = [n[a] / n[0] for a in range(dim)]
+        self.mesh = make_mesh(dim, n, lo, hi)
+        self.f = dg_forcing_init(self.mesh, order, kmax, t_corr, sigma0)
+        self.ncells = 1
+        for a in range(dim):
+            self.ncells *= n[a]
+        self.nm = dg_forcing_num_modes(self.f)
+
+    def __del__(self):
+        f = getattr(self, "f", None)
+        if f and dg_forcing_free is not None and lib is not None:   # see Batch.__del__
+            dg_forcing_free(f)
+            self.f = None
+
+    def modes(self):
+        return dg_forcing_modes(self.f)
+
+    def amplitudes(self):
+        return dg_forcing_get_amplitudes(self.f)
+
+    def set_amplitudes(self, a):
+        dg_forcing_set_amplitudes(self.f, a)
+
+    def update(self, noise, dt):
+        dg_forcing_update(self.f, noise, dt)
+
+    def project(self, out=None, stream=None):
+        if out is None:
+            out = torch.empty(self.ncells * self.dim * self.order ** self.dim, dtype=torch.float64, device="cuda")
+        elif out.numel() != self.ncells * self.dim * self.order ** self.dim:
+            raise ValueError("dg_forcing_project: output has %d elements, expected %d"
+                             % (out.numel(), self.ncells * self.dim * self.order ** self.dim))
+        dg_forcing_project(self.f, out, stream)
+        return out
 
 
 # ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@ Workloads (shapes and value structure of the paper's problems):
     Lecoanet et al. benchmark used in Sec. 6; its reference data is not used).
   * ``sod``            2D shock tube on [0,1]x[0,h*ny], (1,1) | (0.125,0.1).
   * ``gaussian_pulse`` passive-tracer Gaussian at rest on [-0.5,0.5]^2 (periodic images).
+  * ``ou_noise``       seeded standard normal draws for the driving-field updates.
   * ``turbulence``     3D periodic box, rho = 1, c_s = 1, random solenoidal
     velocity on 1 <= |k| <= 3 with amplitude ~ k^(-8/3), rms Mach 0.3, plus a
     solenoidal forcing field on the same band (Sec. 7 setup).
@@ -190,6 +191,13 @@ def gaussian_pulse(order, n=8, t=1.0, eta=1.0 / 128.0, device="cpu", gamma=1.4):
 
     h = 1.0 / n
     return project(fn, 2, (n, n), (-0.5, -0.5), h, order, device)
+
+
+def ou_noise(nmodes, count, seed=2208):
+    """Standard normal draws for `count` Ornstein-Uhlenbeck updates of the
+    driving modes: an array (count, nmodes, 3, 2) from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((count, nmodes, 3, 2))
 
 
 def _solenoidal_modes(rng, kmax, slope):

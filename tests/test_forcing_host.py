@@ -1,0 +1,45 @@
+"""Host side of the driving field (Sec. 7.1) in the library, no GPU needed:
+the mode set and the FP64 Ornstein-Uhlenbeck updates (dg_forcing_update)
+against the oracle's, on the same seeded draws, and argument checks."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2208_11131_amd as dg
+from paper_2208_11131_amd import workloads as W
+
+pytestmark = pytest.mark.skipif(not os.path.exists(dg.LIB_PATH), reason="library not built")
+
+
+@pytest.mark.parametrize("dim,kmax", [(3, 3), (2, 3), (3, 2)])
+def test_modes_and_updates_match_oracle(dim, kmax):
+    drv = dg.Driving(dim, (8,) * dim, 3, kmax=kmax, t_corr=1.0, sigma0=0.8)
+    kv = drv.modes()
+    np.testing.assert_array_equal(kv, O.forcing_modes(dim, kmax))
+    noise = W.ou_noise(len(kv), 12, seed=2208)
+    a_ref = np.zeros((len(kv), 3, 2))
+    for i, dt in enumerate([math.inf] + [0.01] * 11):
+        drv.update(noise[i], dt)
+        a_ref = O.ou_update(dim, kv, a_ref, noise[i], dt, 1.0, 0.8)
+        a = drv.amplitudes()
+        np.testing.assert_allclose(a, a_ref, rtol=0, atol=1e-15 * np.abs(a_ref).max())
+    if dim == 2:
+        assert np.all(a[:, 2] == 0.0)
+
+
+def test_forcing_rejects_bad_arguments():
+    m = dg.make_mesh(3, (4, 4, 4))
+    for args in ((m, 9, 3, 1.0, 1.0), (m, 3, 0, 1.0, 1.0), (m, 3, 5, 1.0, 1.0), (m, 3, 3, 0.0, 1.0),
+                 (m, 3, 3, 1.0, -1.0)):
+        with pytest.raises(dg.DgError):
+            dg.dg_forcing_init(*args)
+    drv = dg.Driving(3, (4, 4, 4), 2)
+    with pytest.raises(ValueError):
+        drv.update(np.zeros((3, 3, 2)), 0.1)
+    with pytest.raises(dg.DgError):
+        drv.update(np.zeros((drv.nm, 3, 2)), -1.0)
+    with pytest.raises(dg.DgError):
+        drv.set_amplitudes(np.full((drv.nm, 3, 2), np.nan))
