@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("forcing", ctypes.POINTER(ctypes.c_double)),
         ("limiter", ctypes.c_int),
         ("tracer", ctypes.c_int), ("eta", ctypes.c_double),
+        ("basis", ctypes.c_int),
     ]
 
 
@@ -71,6 +72,9 @@ def _load():
             "or_step": (None, [P, _D, ctypes.c_double, _D]),
             "or_totals": (None, [P, _D, _D]),
             "or_limit": (ctypes.c_long, [P, _D]),
+            "or_n_modes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+            "or_mode_degrees": (None, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int)]),
             "or_forcing_modes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
             "or_ou_update": (None, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double]),
@@ -97,7 +101,7 @@ class Problem:
     """Mesh, order and physics of one oracle run (mirrors the library's init)."""
 
     def __init__(self, dim, n, h, order, gamma, nu=0.0, kappa=0.0, bc=None, av=None,
-                 cfl=0.5, forcing=None, limiter=False, tracer=False, eta=0.0):
+                 cfl=0.5, forcing=None, limiter=False, tracer=False, eta=0.0, basis=0):
         self.dim, self.order = dim, order
         self.n = tuple(n) + (1,) * (3 - len(n))
         self.h = h
@@ -112,6 +116,7 @@ class Problem:
         self.p.limiter = 1 if limiter else 0
         self.p.tracer = 1 if tracer else 0
         self.p.eta = eta
+        self.p.basis = basis
         self.av = av
         if av is not None:
             self.p.av_on = 1
@@ -124,7 +129,11 @@ class Problem:
         self.set_forcing(forcing)
         self.ncons = dim + 2 + (1 if tracer else 0)
         self.nfields = self.ncons + (1 if av is not None else 0)
-        self.nmodes = order ** dim
+        self.basis = basis
+        if basis == 0:
+            self.nmodes = order ** dim
+        else:
+            self.nmodes = order * (order + 1) // 2 if dim == 2 else order * (order + 1) * (order + 2) // 6
         self.ncells = int(np.prod(self.n[:dim]))
 
     def set_forcing(self, s):
@@ -213,6 +222,20 @@ class Problem:
         wR = np.ascontiguousarray(wR, dtype=np.float64)
         lib.or_recover_face(ctypes.byref(self.p), _ptr(wL), _ptr(wR), axis, _ptr(ut), _ptr(gt))
         return ut, gt
+
+
+def n_modes(order, dim, basis):
+    return _load().or_n_modes(order, dim, basis)
+
+
+def mode_degrees(order, dim, basis):
+    """(M, 3) int array of the degrees of every mode of the basis."""
+    lib = _load()
+    M = lib.or_n_modes(order, dim, basis)
+    out = np.zeros((M, 3), dtype=np.int32)
+    for m in range(M):
+        lib.or_mode_degrees(order, dim, basis, m, out[m].ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return out
 
 
 def forcing_modes(dim, kmax):

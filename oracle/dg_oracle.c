@@ -160,7 +160,8 @@ static long cell_index(const or_params *pr, const int *ijk)
     return c;
 }
 
-/* Mode index l = l_x + p (l_y + p l_z) -> per-dimension degrees. */
+/* Tensor index m = l_x + p (l_y + p l_z) -> per-dimension digits (tensor
+ * modes of Q_n and the Gauss points of a cell). */
 static void mode_degrees(int p, int dim, int m, int *l)
 {
     l[0] = l[1] = l[2] = 0;
@@ -170,6 +171,57 @@ static void mode_degrees(int p, int dim, int m, int *l)
     }
 }
 
+#define OR_MAXMODES ((OR_MAXP) * (OR_MAXP) * (OR_MAXP))
+
+/* Modes per field: the tensor set Q_n (basis 0, (n+1)^d modes) or the
+ * total-degree set P_n (basis 1, sum_a l_a <= n: (n+1)(n+2)/2 in 2D and
+ * (n+1)(n+2)(n+3)/6 in 3D, Sec. 2.3 eqs. N2D and N3D). */
+static int n_modes_b(int p, int d, int basis)
+{
+    if (basis == 0) return ipow(p, d);
+    return d == 2 ? p * (p + 1) / 2 : p * (p + 1) * (p + 2) / 6;
+}
+
+/* Degrees of mode m: Q_n as mode_degrees; P_n in the order l_z, then l_y,
+ * then l_x ascending (l_x fastest) over sum l <= n. */
+static void mode_of(int p, int d, int basis, int m, int *l)
+{
+    if (basis == 0) {
+        mode_degrees(p, d, m, l);
+        return;
+    }
+    const int n = p - 1;
+    int idx = 0;
+    for (int lz = 0; lz <= (d == 3 ? n : 0); ++lz)
+        for (int ly = 0; ly <= n - lz; ++ly)
+            for (int lx = 0; lx <= n - ly - lz; ++lx) {
+                if (idx == m) {
+                    l[0] = lx;
+                    l[1] = ly;
+                    l[2] = lz;
+                    return;
+                }
+                ++idx;
+            }
+    l[0] = l[1] = l[2] = -1;
+}
+
+static int n_modes(const or_params *pr)
+{
+    return n_modes_b(pr->order, pr->dim, pr->basis);
+}
+
+int or_n_modes(int p, int d, int basis)
+{
+    return n_modes_b(p, d, basis);
+}
+
+/* Degrees (l_x, l_y, l_z) of mode m of the basis (for the tests). */
+void or_mode_degrees(int p, int d, int basis, int m, int *l)
+{
+    mode_of(p, d, basis, m, l);
+}
+
 /* Coefficients of the neighbour of cell c across its side (dir a, side s = -1
  * lower, +1 upper).  Periodic boundaries wrap; outflow boundaries (bc 1) use
  * the mirror image of the cell itself, w_ghost(l_a) = (-1)^{l_a} w(l_a);
@@ -177,7 +229,7 @@ static void mode_degrees(int p, int dim, int m, int *l)
  * component normal to the wall negated. */
 static void neighbour_coeffs(const or_params *pr, const double *w, long c, int a, int s, double *out)
 {
-    const int p = pr->order, d = pr->dim, F = n_fields(pr), M = ipow(p, d);
+    const int p = pr->order, d = pr->dim, F = n_fields(pr), M = n_modes(pr);
     int ijk[3];
     cell_coords(pr, c, ijk);
     int t = ijk[a] + s;
@@ -195,7 +247,7 @@ static void neighbour_coeffs(const or_params *pr, const double *w, long c, int a
     for (int f = 0; f < F; ++f)
         for (int m = 0; m < M; ++m) {
             int l[3];
-            mode_degrees(p, d, m, l);
+            mode_of(p, d, pr->basis, m, l);
             double sgn = (l[a] & 1) ? -1.0 : 1.0;
             if (pr->bc[a] == 2 && f == 1 + a) sgn = -sgn;
             out[f * M + m] = sgn * own[f * M + m];
@@ -208,9 +260,9 @@ static void neighbour_coeffs(const or_params *pr, const double *w, long c, int a
 
 /* u(xi) = sum_l w_l phi_l(xi) for all F fields; optionally the xi-derivatives
  * du[b][f] = d u_f / d xi_b (Sec. 2.1, 2.4). */
-static void eval_state(int p, int d, int F, const double *wc, const double *xi, double *u, double *du)
+static void eval_state(int p, int d, int F, int basis, const double *wc, const double *xi, double *u, double *du)
 {
-    const int M = ipow(p, d);
+    const int M = n_modes_b(p, d, basis);
     double Pt[3][OR_MAXP + 2], dPt[3][OR_MAXP + 2];
     for (int a = 0; a < d; ++a) or_legendre(p - 1, xi[a], Pt[a], dPt[a]);
     for (int f = 0; f < F; ++f) {
@@ -220,7 +272,7 @@ static void eval_state(int p, int d, int F, const double *wc, const double *xi, 
     }
     for (int m = 0; m < M; ++m) {
         int l[3];
-        mode_degrees(p, d, m, l);
+        mode_of(p, d, basis, m, l);
         double phi = 1.0;
         for (int a = 0; a < d; ++a) phi *= Pt[a][l[a]];
         double dphi[3] = {0, 0, 0};
@@ -403,6 +455,21 @@ double or_recovery_fraction(int order)
     return (order - 1) <= 2 ? 0.75 : 1.0;
 }
 
+/* Recovery mode r = l_a + (n+2) (l_t1 + p l_t2) (normal degree l_a <= n+1,
+ * transverse degrees <= n) of the basis on K*: every one for Q_n; for P_n
+ * those of total degree <= n+1 (the order n+1 of the cell basis). */
+static int recovery_mode(const or_params *pr, int r)
+{
+    if (pr->basis == 0) return 1;
+    const int p = pr->order;
+    int tot = r % (p + 1), rest = r / (p + 1);
+    for (int s = 0; s < pr->dim - 1; ++s) {
+        tot += rest % p;
+        rest /= p;
+    }
+    return tot <= p;
+}
+
 /* Recovered state and gradient at the face between wL (lower) and wR (upper)
  * along axis a, at the face quadrature points xi_t (p^{d-1} points).
  * q_l = (1/|K*|) int_{K*} u psi_l, psi_l = Pt_{l_a}(xi*) prod_t Pt_{l_t}(xi_t),
@@ -447,10 +514,11 @@ void or_recover_face(const or_params *pr, const double *wL, const double *wR, in
                     or_legendre(p - 1, xq[k], Pt_t[s], NULL);
                 }
                 double u[OR_MAXF];
-                eval_state(p, d, F, wc, xi, u, NULL);
+                eval_state(p, d, F, pr->basis, wc, xi, u, NULL);
                 /* (1/|K*|) int = (1/2) int dxi* * prod_t (1/2) int dxi_t */
                 double W = ws * wt * 0.5 * pow(0.5, nt);
                 for (int r = 0; r < NR; ++r) {
+                    if (!recovery_mode(pr, r)) continue;
                     int la = r % (p + 1), rest = r / (p + 1);
                     double psi = Ps[la];
                     for (int s = 0; s < nt; ++s) {
@@ -476,6 +544,7 @@ void or_recover_face(const or_params *pr, const double *wL, const double *wR, in
         for (int f = 0; f < F; ++f) {
             double val = 0, dn = 0, dt[2] = {0, 0};
             for (int r = 0; r < NR; ++r) {
+                if (!recovery_mode(pr, r)) continue;
                 int la = r % (p + 1), rest = r / (p + 1);
                 int lt[2] = {0, 0};
                 for (int s = 0; s < nt; ++s) {
@@ -579,9 +648,9 @@ static void face_flux_m(const or_params *pr, const double *wL, const double *wR,
         }
         double uL[OR_MAXF], uR[OR_MAXF];
         xi[a] = 1.0;
-        eval_state(p, d, F, wL, xi, uL, NULL);
+        eval_state(p, d, F, pr->basis, wL, xi, uL, NULL);
         xi[a] = -1.0;
-        eval_state(p, d, F, wR, xi, uR, NULL);
+        eval_state(p, d, F, pr->basis, wR, xi, uR, NULL);
         if (absmode)
             hllc_terms_abs(d, Fc, pr->gamma, uL, uR, a, Fh + k * Fc);
         else
@@ -609,11 +678,13 @@ static void face_flux_m(const or_params *pr, const double *wL, const double *wR,
 /* Sensor (Sec. 4.1)                                                          */
 /* ------------------------------------------------------------------------- */
 
-/* "Top" modes are those absent at the next lower order: max_a l_a = n. */
-static int is_top_mode(int p, int d, int m)
+/* "Top" modes are those absent at the next lower order: max_a l_a = n for
+ * Q_n, total degree n for P_n. */
+static int is_top_mode(int p, int d, int basis, int m)
 {
     int l[3];
-    mode_degrees(p, d, m, l);
+    mode_of(p, d, basis, m, l);
+    if (basis == 1) return l[0] + l[1] + l[2] == p - 1;
     for (int a = 0; a < d; ++a)
         if (l[a] == p - 1) return 1;
     return 0;
@@ -621,27 +692,39 @@ static int is_top_mode(int p, int d, int m)
 
 /* S = sum_top w^2 / sum_all w^2 of the density coefficients
  * (eq. discontinuity_sensor2); S = 0 when the denominator vanishes. */
-double or_sensor(int p, int d, const double *wrho)
+static double sensor_b(int p, int d, int basis, const double *wrho)
 {
-    const int M = ipow(p, d);
+    const int M = n_modes_b(p, d, basis);
     double all = 0, top = 0;
     for (int m = 0; m < M; ++m) {
         all += wrho[m] * wrho[m];
-        if (is_top_mode(p, d, m)) top += wrho[m] * wrho[m];
+        if (is_top_mode(p, d, basis, m)) top += wrho[m] * wrho[m];
     }
     return all > 0.0 ? top / all : 0.0;
 }
 
+double or_sensor(int p, int d, const double *wrho)
+{
+    return sensor_b(p, d, 0, wrho);
+}
+
 /* d ln S / dt from w and dw/dt of the density: Sdot / S with
  * Sdot = 2 [(sum_top w wd)(sum_all w^2) - (sum_top w^2)(sum_all w wd)] / (sum_all w^2)^2. */
+static double sensor_rate_b(int p, int d, int basis, const double *wrho, const double *wdrho);
+
 double or_sensor_rate(int p, int d, const double *wrho, const double *wdrho)
 {
-    const int M = ipow(p, d);
+    return sensor_rate_b(p, d, 0, wrho, wdrho);
+}
+
+static double sensor_rate_b(int p, int d, int basis, const double *wrho, const double *wdrho)
+{
+    const int M = n_modes_b(p, d, basis);
     double A = 0, T = 0, a = 0, t = 0;
     for (int m = 0; m < M; ++m) {
         A += wrho[m] * wrho[m];
         a += wrho[m] * wdrho[m];
-        if (is_top_mode(p, d, m)) {
+        if (is_top_mode(p, d, basis, m)) {
             T += wrho[m] * wrho[m];
             t += wrho[m] * wdrho[m];
         }
@@ -664,7 +747,7 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
                      double *R_out_c, int absmode)
 {
     const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = n_cons(pr);
-    const int M = ipow(p, d), NP = M;
+    const int M = n_modes(pr), NP = ipow(p, d);
     const double h = pr->h;
     const double pref = pow(2.0, 1 - d) / h;     /* 2^(1-d)/h */
     const double spref = pow(2.0, -d);           /* 2^(-d): source projection */
@@ -676,7 +759,7 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
     {
         const double *wc = w + c * (long)F * M;
         for (int i = 0; i < F * M; ++i) out[i] = 0.0;
-        double S_cur = or_sensor(p, d, wc);
+        double S_cur = sensor_b(p, d, pr->basis, wc);
         double wig = 0.0;
         if (pr->av_on && R_prev && S_cur > pr->s_onset / ((double)p * p))
             wig = pr->f_w * fmax(0.0, R_prev[c]);
@@ -691,7 +774,7 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
                 gj *= wg[jj[a]];
             }
             double u[OR_MAXF], dxi[3 * OR_MAXF], g[3 * OR_MAXF];
-            eval_state(p, d, F, wc, xi, u, grad ? dxi : NULL);
+            eval_state(p, d, F, pr->basis, wc, xi, u, grad ? dxi : NULL);
             if (grad)
                 for (int i = 0; i < d * F; ++i) g[i] = dxi[i] * 2.0 / h; /* physical gradient */
             double flux[3][6];
@@ -723,7 +806,7 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
                 double s[3] = {0, 0, 0};
                 for (int m = 0; m < M; ++m) {
                     int l[3];
-                    mode_degrees(p, d, m, l);
+                    mode_of(p, d, pr->basis, m, l);
                     double phi = 1.0;
                     for (int a = 0; a < d; ++a) {
                         double Pt[OR_MAXP + 2];
@@ -744,7 +827,7 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
             for (int a = 0; a < d; ++a) or_legendre(p - 1, xi[a], Pt[a], dPt[a]);
             for (int m = 0; m < M; ++m) {
                 int l[3];
-                mode_degrees(p, d, m, l);
+                mode_of(p, d, pr->basis, m, l);
                 double phi = 1.0;
                 for (int a = 0; a < d; ++a) phi *= Pt[a][l[a]];
                 for (int a = 0; a < d; ++a) {
@@ -788,7 +871,7 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
                     for (int b = 0; b < d; ++b) or_legendre(p - 1, xi[b], Pt[b], NULL);
                     for (int m = 0; m < M; ++m) {
                         int l[3];
-                        mode_degrees(p, d, m, l);
+                        mode_of(p, d, pr->basis, m, l);
                         double phi = 1.0;
                         for (int b = 0; b < d; ++b) phi *= Pt[b][l[b]];
                         for (int f = 0; f < Fc; ++f)
@@ -804,14 +887,14 @@ static void rhs_cell(const or_params *pr, const double *w, const double *R_prev,
          * below it S is at rounding level and its log-rate is noise (the
          * wiggle trigger of Sec. 4.1 acts only above S_onset). */
         if (R_out_c && pr->av_on && !absmode)
-            *R_out_c = (S_cur > pr->s_onset / ((double)p * p)) ? or_sensor_rate(p, d, wc, out) : 0.0;
+            *R_out_c = (S_cur > pr->s_onset / ((double)p * p)) ? sensor_rate_b(p, d, pr->basis, wc, out) : 0.0;
     }
 #undef ABSM
 }
 
 void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *wdot, double *R_out)
 {
-    const int M = ipow(pr->order, pr->dim), F = n_fields(pr);
+    const int M = n_modes(pr), F = n_fields(pr);
     const long NC = n_cells(pr);
 #pragma omp parallel for schedule(dynamic, 4)
     for (long c = 0; c < NC; ++c) rhs_cell(pr, w, R_prev, c, wdot + c * (long)F * M, R_out ? R_out + c : NULL, 0);
@@ -822,7 +905,7 @@ void or_rhs(const or_params *pr, const double *w, const double *R_prev, double *
 void or_rhs_cells(const or_params *pr, const double *w, const double *R_prev, long ncells_sel, const long *cells,
                   double *out)
 {
-    const int M = ipow(pr->order, pr->dim), F = n_fields(pr);
+    const int M = n_modes(pr), F = n_fields(pr);
 #pragma omp parallel for schedule(dynamic, 1)
     for (long i = 0; i < ncells_sel; ++i) rhs_cell(pr, w, R_prev, cells[i], out + i * (long)F * M, NULL, 0);
 }
@@ -837,7 +920,7 @@ void or_rhs_cells(const or_params *pr, const double *w, const double *R_prev, lo
 void or_rhs_abs(const or_params *pr, const double *w, const double *R_prev, long ncells_sel, const long *cells,
                 double *out)
 {
-    const int M = ipow(pr->order, pr->dim), F = n_fields(pr);
+    const int M = n_modes(pr), F = n_fields(pr);
     const long n = cells ? ncells_sel : n_cells(pr);
 #pragma omp parallel for schedule(dynamic, 1)
     for (long i = 0; i < n; ++i) rhs_cell(pr, w, R_prev, cells ? cells[i] : i, out + i * (long)F * M, NULL, 1);
@@ -922,7 +1005,7 @@ static void forcing_value(int dim, int nm, const int *kv, const double *amp, con
 void or_forcing_project(const or_params *pr, const double *lo, int nm, const int *kv, const double *amp,
                         double *s)
 {
-    const int p = pr->order, d = pr->dim, M = ipow(p, d);
+    const int p = pr->order, d = pr->dim, M = n_modes(pr);
     const long NC = n_cells(pr);
     const int nq = 16;
     double xq[16], wq[16];
@@ -950,7 +1033,7 @@ void or_forcing_project(const or_params *pr, const double *lo, int nm, const int
             for (int a = 0; a < d; ++a) or_legendre(p - 1, xi[a], Pt[a], NULL);
             for (int m = 0; m < M; ++m) {
                 int l[3];
-                mode_degrees(p, d, m, l);
+                mode_of(p, d, pr->basis, m, l);
                 double phi = 1.0;
                 for (int a = 0; a < d; ++a) phi *= Pt[a][l[a]];
                 for (int cc = 0; cc < d; ++cc) sc[cc * M + m] += wt * phi * sv[cc];
@@ -1017,7 +1100,7 @@ static double pressure_of(int d, double gamma, const double *u)
  * leaving the cell mean).  Returns 1 if the cell was changed. */
 static int limit_cell(const or_params *pr, double *wc)
 {
-    const int p = pr->order, d = pr->dim, F = n_fields(pr), M = ipow(p, d);
+    const int p = pr->order, d = pr->dim, F = n_fields(pr), M = n_modes(pr);
     double xi[3 * (OR_MAXP * OR_MAXP * OR_MAXP + 6 * OR_MAXP * OR_MAXP)];
     const int np = limiter_points(p, d, xi);
     double um[OR_MAXF];
@@ -1030,7 +1113,7 @@ static int limit_cell(const or_params *pr, double *wc)
     double rmin = rbar;
     for (int k = 0; k < np; ++k) {
         double u[OR_MAXF];
-        eval_state(p, d, F, wc, xi + 3 * k, u, NULL);
+        eval_state(p, d, F, pr->basis, wc, xi + 3 * k, u, NULL);
         if (u[0] < rmin) rmin = u[0];
     }
     if (rmin < rb) {
@@ -1045,7 +1128,7 @@ static int limit_cell(const or_params *pr, double *wc)
         double pmin = pbar;
         for (int k = 0; k < np; ++k) {
             double u[OR_MAXF];
-            eval_state(p, d, F, wc, xi + 3 * k, u, NULL);
+            eval_state(p, d, F, pr->basis, wc, xi + 3 * k, u, NULL);
             double pk = pressure_of(d, pr->gamma, u);
             if (!(pk >= pmin)) pmin = pk;
         }
@@ -1066,7 +1149,7 @@ static int limit_cell(const or_params *pr, double *wc)
  * changed. */
 long or_limit(const or_params *pr, double *w)
 {
-    const int F = n_fields(pr), M = ipow(pr->order, pr->dim);
+    const int F = n_fields(pr), M = n_modes(pr);
     const long NC = n_cells(pr);
     long nchg = 0;
 #pragma omp parallel for reduction(+ : nchg) schedule(dynamic, 16)
@@ -1082,20 +1165,20 @@ long or_limit(const or_params *pr, double *w)
  * dt = f_CFL h / (2 p (c_max + v_max))  (Sec. 2.5, eq. timestep). */
 double or_max_dt(const or_params *pr, const double *w, double *cmax_out, double *vmax_out)
 {
-    const int p = pr->order, d = pr->dim, F = n_fields(pr), M = ipow(p, d);
+    const int p = pr->order, d = pr->dim, F = n_fields(pr), M = n_modes(pr), NP = ipow(p, d);
     const long NC = n_cells(pr);
     double xg[OR_MAXP + 2], wg[OR_MAXP + 2];
     or_gauss(p, xg, wg);
     double cmax = 0.0, vmax = 0.0;
 #pragma omp parallel for reduction(max : cmax, vmax)
     for (long c = 0; c < NC; ++c) {
-        for (int j = 0; j < M; ++j) {
+        for (int j = 0; j < NP; ++j) {
             int jj[3];
             mode_degrees(p, d, j, jj);
             double xi[3] = {0, 0, 0};
             for (int a = 0; a < d; ++a) xi[a] = xg[jj[a]];
             double u[OR_MAXF];
-            eval_state(p, d, F, w + c * (long)F * M, xi, u, NULL);
+            eval_state(p, d, F, pr->basis, w + c * (long)F * M, xi, u, NULL);
             double v2 = 0;
             for (int i = 0; i < d; ++i) v2 += (u[1 + i] / u[0]) * (u[1 + i] / u[0]);
             double cs = sound_speed(d, pr->gamma, u);
@@ -1124,7 +1207,7 @@ void or_step(const or_params *pr, double *w, double dt, double *R_state)
     do {                                  \
         if (pr->limiter) or_limit(pr, x); \
     } while (0)
-    const int p = pr->order, d = pr->dim, F = n_fields(pr), M = ipow(p, d);
+    const int p = pr->order, F = n_fields(pr), M = n_modes(pr);
     const long NC = n_cells(pr), N = NC * F * M;
     double *R_new = NULL;
     if (pr->av_on) R_new = (double *)calloc(NC, sizeof(double));
@@ -1200,7 +1283,7 @@ void or_step(const or_params *pr, double *w, double dt, double *R_state)
  * Neumaier-compensated. */
 void or_totals(const or_params *pr, const double *w, double *out)
 {
-    const int p = pr->order, d = pr->dim, F = n_fields(pr), Fc = n_cons(pr), M = ipow(p, d);
+    const int d = pr->dim, F = n_fields(pr), Fc = n_cons(pr), M = n_modes(pr);
     const long NC = n_cells(pr);
     double vol = pow(pr->h, d);
     for (int f = 0; f < Fc; ++f) {

@@ -21,6 +21,7 @@ typedef struct {
     int limiter;       /* positivity limiter after every RK stage (Sec. 4.2) */
     int tracer;        /* passive tracer field c rho after e (Sec. 3.4) */
     double eta;        /* its diffusivity */
+    int basis;         /* 0 tensor set Q_n, 1 total-degree set P_n (Sec. 2.3) */
 } or_params;
 
 void or_legendre(int lmax, double x, double *Pt, double *dPt);
@@ -41,6 +42,8 @@ int or_rk_stages(int order);
 void or_step(const or_params *pr, double *w, double dt, double *R_state);
 void or_totals(const or_params *pr, const double *w, double *out);
 long or_limit(const or_params *pr, double *w);
+int or_n_modes(int p, int d, int basis);
+void or_mode_degrees(int p, int d, int basis, int m, int *l);
 int or_forcing_modes(int dim, int kmax, int *kv);
 void or_ou_update(int dim, int nm, const int *kv, double *amp, const double *noise, double dt, double t_corr,
                   double sigma0);
