@@ -11,7 +11,9 @@
  *   - Order p (the `order` argument) = n + 1 = modes = Gauss points per axis,
  *     1 <= p <= 8 (Sec. 2.3, 2.4).  Modes per field: p^dim (tensor set Q_n).
  *   - State layout (device, float64, C-contiguous): w[cell][field][mode],
- *     cell = i + n0 (j + n1 k), mode = l_x + p (l_y + p l_z); fields
+ *     cell = i + n0 (j + n1 k), mode = l_x + p (l_y + p l_z) (tensor basis;
+ *     the total-degree basis of dg_options.basis = 1 stores its modes as
+ *     stated there); fields
  *     (rho, rho v_x, rho v_y[, rho v_z], e[, c rho][, alpha]): dim + 2
  *     conserved fields, the passive tracer c rho when enabled (Sec. 3.4), and
  *     the artificial-viscosity field alpha when AV is enabled (Sec. 4.1).
@@ -88,8 +90,13 @@ typedef struct {
  * time step and totals stay FP64). */
 typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_BULK = 1 } dg_precision;
 
-/* Options (NULL = defaults): precision FP64; basis 0 = tensor set Q_n (the
- * only basis of this build); cfl = f_CFL of eq. timestep (default 0.5);
+/* Options (NULL = defaults): precision FP64; basis 0 = tensor set Q_n
+ * (p^dim modes per field), 1 = total-degree set P_n of Sec. 2.3 (the modes
+ * of degree l_x + l_y [+ l_z] <= n: (n+1)(n+2)/2 in 2D, (n+1)(n+2)(n+3)/6 in
+ * 3D, stored in the order l_z, l_y, l_x ascending with l_x fastest; Euler and
+ * Navier-Stokes only; the interface recovery then uses the basis of total
+ * degree <= n+1 and the sensor's top modes are those of total degree n); cfl =
+ * f_CFL of eq. timestep (default 0.5);
  * launch tiles (0 = built-in tuned table): cells per volume block, faces per
  * face-kernel pencil, threads per volume / face block (multiples of 64,
  * at most 512).  Results do not depend on the tiles.  limiter = 1: the
@@ -128,18 +135,21 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
 /* Free the context and its device buffers (NULL is ignored). */
 void dg_free(dg_ctx *ctx);
 
-/* Number of doubles of a state array: cells * fields * order^dim. */
+/* Number of doubles of a state array: cells * fields * dg_num_modes. */
 size_t dg_state_len(const dg_ctx *ctx);
 /* Number of fields per cell (dim + 2, + 1 with the tracer, + 1 with AV). */
 int dg_num_fields(const dg_ctx *ctx);
 /* Number of conserved fields (dim + 2, + 1 with the tracer): the values
  * dg_conserved_totals returns. */
 int dg_num_conserved(const dg_ctx *ctx);
+/* Stored modes per field: p^dim (Q_n) or the total-degree count (P_n). */
+int dg_num_modes(const dg_ctx *ctx);
 
 /* Shape of the context (host pointers, any may be NULL): dimension, order p,
  * number of cells and fields per cell.  A state array holds
- * ncells * nfields * p^dim doubles, a forcing array (dg_set_forcing)
- * ncells * dim * p^dim, a sensor-rate array ncells.  DG_EINVAL for NULL ctx. */
+ * ncells * nfields * dg_num_modes doubles, a forcing array (dg_set_forcing)
+ * ncells * dim * dg_num_modes, a sensor-rate array ncells.  DG_EINVAL for
+ * NULL ctx. */
 dg_status dg_shape(const dg_ctx *ctx, int *dim, int *order, long long *ncells, int *nfields);
 
 /* wdot = dw/dt of the weight equations (Sec. 2.2 eq. weight_evolution,
@@ -226,10 +236,11 @@ dg_status dg_set_forcing(dg_ctx *ctx, const double *s_coeffs);
 typedef struct dg_forcing dg_forcing;
 
 /* Driving field on the box of `mesh` (periodic unit-length box expected) for
- * order p; 1 <= kmax <= 4, t_corr > 0, sigma0 >= 0.  Amplitudes start at 0.
- * Host allocation only (the device table is allocated by the first
- * dg_forcing_project).  *out = NULL on error. */
-dg_status dg_forcing_init(const dg_mesh *mesh, int order, int kmax, double t_corr, double sigma0,
+ * order p and basis (0 tensor, 1 total degree: the layout of the projected
+ * coefficients, as dg_options.basis); 1 <= kmax <= 4, t_corr > 0,
+ * sigma0 >= 0.  Amplitudes start at 0.  Host allocation only (the device
+ * table is allocated by the first dg_forcing_project).  *out = NULL on error. */
+dg_status dg_forcing_init(const dg_mesh *mesh, int order, int basis, int kmax, double t_corr, double sigma0,
                           dg_forcing **out);
 void dg_forcing_free(dg_forcing *f);
 /* Number of modes (one per +-k pair), and their wave vectors (host int[nm][3]). */
@@ -245,9 +256,10 @@ dg_status dg_forcing_set_amplitudes(dg_forcing *f, const double *amp);
  * solenoidal projection.  dt = +inf draws from the stationary law.  Host only. */
 dg_status dg_forcing_update(dg_forcing *f, const double *noise, double dt);
 /* DG coefficients of s on every cell, s_coeffs (device, caller-owned,
- * [cell][dim][p^dim] doubles): (1/|K|) int_K s phi_l, each mode's cell
+ * [cell][dim][modes] doubles): (1/|K|) int_K s phi_l, each mode's cell
  * integral factorised into per-axis factors (1/2) int exp(i pi k_a h xi)
- * Pt_l(xi) dxi tabulated on the host.  Copies the amplitudes to the device
+ * Pt_l(xi) dxi tabulated on the host (modes in the layout of the basis).
+ * Copies the amplitudes to the device
  * (synchronising `stream`), then enqueues one kernel. */
 dg_status dg_forcing_project(dg_forcing *f, double *s_coeffs, void *stream);
 

@@ -58,6 +58,7 @@ _SIGS = {
     "dg_state_len": (ctypes.c_size_t, [_V]),
     "dg_num_fields": (ctypes.c_int, [_V]),
     "dg_num_conserved": (ctypes.c_int, [_V]),
+    "dg_num_modes": (ctypes.c_int, [_V]),
     "dg_shape": (ctypes.c_int, [_V, _I, _I, ctypes.POINTER(ctypes.c_longlong), _I]),
     "dg_rhs": (ctypes.c_int, [_V, _V, _V, _V]),
     "dg_step": (ctypes.c_int, [_V, _V, ctypes.c_double, _V]),
@@ -83,8 +84,8 @@ _SIGS = {
     "dg_batch_dt": (ctypes.c_int, [_V, _D, _V]),
     "dg_batch_box": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(_V)]),
     "dg_batch_size": (ctypes.c_int, [_V]),
-    "dg_forcing_init": (ctypes.c_int, [ctypes.POINTER(dg_mesh), ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                       ctypes.c_double, ctypes.POINTER(_V)]),
+    "dg_forcing_init": (ctypes.c_int, [ctypes.POINTER(dg_mesh), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, ctypes.POINTER(_V)]),
     "dg_forcing_free": (None, [_V]),
     "dg_forcing_num_modes": (ctypes.c_int, [_V]),
     "dg_forcing_modes": (ctypes.c_int, [_V, _I]),
@@ -194,6 +195,10 @@ def dg_num_conserved(ctx):
     return lib().dg_num_conserved(ctx)
 
 
+def dg_num_modes(ctx):
+    return lib().dg_num_modes(ctx)
+
+
 def dg_shape(ctx):
     """(dim, order, ncells, nfields) of a context."""
     d, o, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -245,7 +250,7 @@ def dg_set_forcing(ctx, s):
         _chk(lib().dg_set_forcing(ctx, None), "dg_set_forcing")
         return
     dim, order, ncells, _ = dg_shape(ctx)
-    _chk(lib().dg_set_forcing(ctx, _dptr(s, ncells * dim * order ** dim)), "dg_set_forcing")
+    _chk(lib().dg_set_forcing(ctx, _dptr(s, ncells * dim * dg_num_modes(ctx))), "dg_set_forcing")
 
 
 def dg_set_sensor_rate(ctx, R, stream=None):
@@ -357,9 +362,10 @@ class Batch:
         return dg_check(dg_batch_box(self.b, i), stream)
 
 
-def dg_forcing_init(mesh, order, kmax, t_corr, sigma0):
+def dg_forcing_init(mesh, order, kmax, t_corr, sigma0, basis=0):
     f = _V()
-    _chk(lib().dg_forcing_init(ctypes.byref(mesh), order, kmax, t_corr, sigma0, ctypes.byref(f)), "dg_forcing_init")
+    _chk(lib().dg_forcing_init(ctypes.byref(mesh), order, basis, kmax, t_corr, sigma0, ctypes.byref(f)),
+         "dg_forcing_init")
     return f
 
 
@@ -410,16 +416,20 @@ def dg_forcing_project(f, s, stream=None):
 class Driving:
     """Ornstein-Uhlenbeck driving field of one box (one dg_forcing)."""
 
-    def __init__(self, dim, n, order, kmax=3, t_corr=1.0, sigma0=1.0, lo=None, hi=None):
+    def __init__(self, dim, n, order, kmax=3, t_corr=1.0, sigma0=1.0, lo=None, hi=None, basis=0):
         self.dim, self.order = dim, order
         if hi is None:
             hi = [n[a] / n[0] for a in range(dim)]
         self.mesh = make_mesh(dim, n, lo, hi)
-        self.f = dg_forcing_init(self.mesh, order, kmax, t_corr, sigma0)
+        self.f = dg_forcing_init(self.mesh, order, kmax, t_corr, sigma0, basis)
         self.ncells = 1
         for a in range(dim):
             self.ncells *= n[a]
         self.nm = dg_forcing_num_modes(self.f)
+        if basis == 0:
+            self.nmodes = order ** dim
+        else:
+            self.nmodes = order * (order + 1) // 2 if dim == 2 else order * (order + 1) * (order + 2) // 6
 
     def __del__(self):
         f = getattr(self, "f", None)
@@ -440,11 +450,11 @@ class Driving:
         dg_forcing_update(self.f, noise, dt)
 
     def project(self, out=None, stream=None):
+        n = self.ncells * self.dim * self.nmodes
         if out is None:
-            out = torch.empty(self.ncells * self.dim * self.order ** self.dim, dtype=torch.float64, device="cuda")
-        elif out.numel() != self.ncells * self.dim * self.order ** self.dim:
-            raise ValueError("dg_forcing_project: output has %d elements, expected %d"
-                             % (out.numel(), self.ncells * self.dim * self.order ** self.dim))
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+        elif out.numel() != n:
+            raise ValueError("dg_forcing_project: output has %d elements, expected %d" % (out.numel(), n))
         dg_forcing_project(self.f, out, stream)
         return out
 
@@ -462,7 +472,7 @@ class Solver:
 
     def __init__(self, dim, n, order, gamma, nu=0.0, kappa=0.0, lo=None, hi=None, bc=None, av=None,
                  precision="fp64", cfl=0.5, cells_per_block=0, faces_per_block=0, vol_threads=0,
-                 face_threads=0, limiter=False, tracer=False, eta=0.0):
+                 face_threads=0, limiter=False, tracer=False, eta=0.0, basis=0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the DG library runs on the GPU only")
         self.dim, self.order = dim, order
@@ -485,12 +495,13 @@ class Solver:
         opt.limiter = 1 if limiter else 0
         opt.tracer = 1 if tracer else 0
         opt.tracer_eta = eta
+        opt.basis = basis
         self.ctx = dg_init(self.mesh, order, gamma, nu, kappa, avp, opt)
         self.nfields = dg_num_fields(self.ctx)
         self.ncells = 1
         for a in range(dim):
             self.ncells *= n[a]
-        self.nmodes = order ** dim
+        self.nmodes = dg_num_modes(self.ctx)
         self._forcing = None
 
     @property

@@ -24,6 +24,13 @@ struct Tab {
     T rvR[MAXP];        //   (normal mode index m, per transverse mode)
     T rdL[MAXP];        // recovered d/dxi* at the face (scale by 1/(f h))
     T rdR[MAXP];
+    // total-degree basis P_n: the same four vectors for the lines of
+    // transverse degree tau (data of normal degree <= n - tau, recovered to
+    // normal degree n + 1 - tau), indexed [tau][m]
+    T prvL[MAXP][MAXP];
+    T prvR[MAXP][MAXP];
+    T prdL[MAXP][MAXP];
+    T prdR[MAXP][MAXP];
 };
 
 // Physics and discretisation constants of one context (FP64; kernels convert).

@@ -69,7 +69,8 @@ constexpr int kMaxP = 8;
 }  // namespace
 
 struct dg_forcing {
-    int dim, P, NP;
+    int dim, P, NP;    // NP: stored modes per component (p^dim, or the total-degree count)
+    int basis;
     int n[3];
     double lo[3], h;
     long long ncells;
@@ -112,11 +113,13 @@ void build_static(dg_forcing *f)
 }
 
 // s[(cell * D + c) * NP + m] = sum_i 2 Re(a_ic prod_a e^{2 pi i k_ia x_ca} J(k_ia, l_a)),
-// one thread per (cell, mode m = l_x + p (l_y + p l_z)).
+// one thread per (cell, stored mode m): m = l_x + p (l_y + p l_z) for the
+// tensor basis; for the total-degree basis the modes of degree <= p - 1 in
+// the order l_z, l_y, l_x ascending (l_x fastest).
 template <int D>
 __global__ void __launch_bounds__(256) forcing_project_kernel(const double *__restrict__ tab, int nm, int kmax,
-                                                              int P, int NP, int n0, int n1, double lo0, double lo1,
-                                                              double lo2, double h, long long ncells,
+                                                              int P, int NP, int basis, int n0, int n1, double lo0,
+                                                              double lo1, double lo2, double h, long long ncells,
                                                               double *__restrict__ s)
 {
     const long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,6 +127,20 @@ __global__ void __launch_bounds__(256) forcing_project_kernel(const double *__re
     const long long cell = item / NP;
     const int m = (int)(item - cell * NP);
     int l[3] = {m % P, (m / P) % P, m / (P * P)};
+    if (basis == 1) {
+        int r = m;
+        l[0] = l[1] = l[2] = 0;
+        for (int lz = 0; lz < (D == 3 ? P : 1); ++lz)
+            for (int ly = 0; ly < P - lz; ++ly) {
+                const int nl = P - ly - lz;
+                if (r >= 0 && r < nl) {
+                    l[0] = r;
+                    l[1] = ly;
+                    l[2] = lz;
+                }
+                r -= nl;
+            }
+    }
     const long long r0 = cell / n0;
     const int ijk[3] = {(int)(cell - r0 * n0), (int)(r0 % n1), (int)(r0 / n1)};
     const double lo[3] = {lo0, lo1, lo2};
@@ -169,11 +186,13 @@ __global__ void __launch_bounds__(256) forcing_project_kernel(const double *__re
 
 extern "C" {
 
-dg_status dg_forcing_init(const dg_mesh *mesh, int order, int kmax, double t_corr, double sigma0, dg_forcing **out)
+dg_status dg_forcing_init(const dg_mesh *mesh, int order, int basis, int kmax, double t_corr, double sigma0,
+                          dg_forcing **out)
 {
     if (!out) return DG_EINVAL;
     *out = nullptr;
     if (!mesh || (mesh->dim != 2 && mesh->dim != 3) || order < 1 || order > kMaxP) return DG_EINVAL;
+    if (basis != 0 && basis != 1) return DG_EINVAL;
     if (kmax < 1 || kmax > kMaxK || !(t_corr > 0.0) || !(sigma0 >= 0.0) || !std::isfinite(sigma0)) return DG_EINVAL;
     const int d = mesh->dim;
     double h = 0.0;
@@ -192,8 +211,10 @@ dg_status dg_forcing_init(const dg_mesh *mesh, int order, int kmax, double t_cor
     try {
         f->dim = d;
         f->P = order;
+        f->basis = basis;
         f->NP = 1;
         for (int a = 0; a < d; ++a) f->NP *= order;
+        if (basis == 1) f->NP = d == 2 ? order * (order + 1) / 2 : order * (order + 1) * (order + 2) / 6;
         for (int a = 0; a < 3; ++a) {
             f->n[a] = a < d ? mesh->n[a] : 1;
             f->lo[a] = a < d ? mesh->lo[a] : 0.0;
@@ -310,10 +331,10 @@ dg_status dg_forcing_project(dg_forcing *f, double *s, void *stream)
     const dim3 grid((unsigned)((items + 255) / 256)), block(256);
     const void *fn = f->dim == 2 ? (const void *)&forcing_project_kernel<2> : (const void *)&forcing_project_kernel<3>;
     const double *t = f->d_tab;
-    int nm = f->nm, kmax = f->kmax, P = f->P, NP = f->NP, n0 = f->n[0], n1 = f->n[1];
+    int nm = f->nm, kmax = f->kmax, P = f->P, NP = f->NP, basis = f->basis, n0 = f->n[0], n1 = f->n[1];
     double lo0 = f->lo[0], lo1 = f->lo[1], lo2 = f->lo[2], h = f->h;
     long long nc = f->ncells;
-    void *args[] = {&t, &nm, &kmax, &P, &NP, &n0, &n1, &lo0, &lo1, &lo2, &h, &nc, &s};
+    void *args[] = {&t, &nm, &kmax, &P, &NP, &basis, &n0, &n1, &lo0, &lo1, &lo2, &h, &nc, &s};
     if (hipLaunchKernel(fn, grid, block, args, 0, st) != hipSuccess) return DG_EDEVICE;
     return DG_OK;
 }

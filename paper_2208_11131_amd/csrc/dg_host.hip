@@ -90,6 +90,12 @@ void round_tab(const Tab<LD> &s, Tab<T> &d)
         d.rvR[i] = (T)s.rvR[i];
         d.rdL[i] = (T)s.rdL[i];
         d.rdR[i] = (T)s.rdR[i];
+        for (int j = 0; j < MAXP; ++j) {
+            d.prvL[i][j] = (T)s.prvL[i][j];
+            d.prvR[i][j] = (T)s.prvR[i][j];
+            d.prdL[i][j] = (T)s.prdL[i][j];
+            d.prdR[i][j] = (T)s.prdR[i][j];
+        }
     }
 }
 
@@ -145,31 +151,41 @@ void build_tab(int P, Tab<LD> &t)
     LD xq[24], wq[24], P0[64], dP0[64];
     gauss_ld(20, xq, wq);
     sleg(P, 0.0L, P0, dP0);
-    for (int m = 0; m < P; ++m) {
-        LD vl = 0, vr = 0, dl = 0, dr = 0;
+    LD AL[MAXP + 1][MAXP], AR[MAXP + 1][MAXP];
+    for (int m = 0; m < P; ++m)
         for (int la = 0; la <= P; ++la) {
-            LD AL = 0, AR = 0;
+            LD sl = 0, sr = 0;
             for (int q = 0; q < 20; ++q) {
                 LD a[64], da[64], b[64], db[64];
                 const LD xsL = 0.5L * (xq[q] - 1.0L);   // [-1, 0]
                 const LD xsR = 0.5L * (xq[q] + 1.0L);   // [0, 1]
                 sleg(P, xsL, a, da);
                 sleg(P - 1, 2.0L * f * xsL + 1.0L, b, db);
-                AL += 0.5L * wq[q] * 0.5L * a[la] * b[m];
+                sl += 0.5L * wq[q] * 0.5L * a[la] * b[m];
                 sleg(P, xsR, a, da);
                 sleg(P - 1, 2.0L * f * xsR - 1.0L, b, db);
-                AR += 0.5L * wq[q] * 0.5L * a[la] * b[m];
+                sr += 0.5L * wq[q] * 0.5L * a[la] * b[m];
             }
-            vl += AL * P0[la];
-            vr += AR * P0[la];
-            dl += AL * dP0[la];
-            dr += AR * dP0[la];
+            AL[la][m] = sl;
+            AR[la][m] = sr;
         }
-        t.rvL[m] = vl;
-        t.rvR[m] = vr;
-        t.rdL[m] = dl;
-        t.rdR[m] = dr;
-    }
+    // recovered expansion truncated at normal degree lmax: value and
+    // xi*-derivative at the face of the sides' contributions
+    auto vectors = [&](int lmax, int m, LD *vl, LD *vr, LD *dl, LD *dr) {
+        *vl = *vr = *dl = *dr = 0;
+        for (int la = 0; la <= lmax; ++la) {
+            *vl += AL[la][m] * P0[la];
+            *vr += AR[la][m] * P0[la];
+            *dl += AL[la][m] * dP0[la];
+            *dr += AR[la][m] * dP0[la];
+        }
+    };
+    for (int m = 0; m < P; ++m) vectors(P, m, &t.rvL[m], &t.rvR[m], &t.rdL[m], &t.rdR[m]);
+    // total-degree basis: transverse degree tau leaves normal degrees
+    // m <= n - tau, recovered to n + 1 - tau
+    for (int tau = 0; tau < P; ++tau)
+        for (int m = 0; m + tau < P; ++m)
+            vectors(P - tau, m, &t.prvL[tau][m], &t.prvR[tau][m], &t.prdL[tau][m], &t.prdR[tau][m]);
 }
 
 struct Tables {
@@ -353,6 +369,7 @@ const TileEntry *find_tiles(int dim, int order, int prec, int phys, int forced)
 
 struct dg_ctx {
     int dim, P, F, Fc, NP, K;
+    int NM;      // stored modes per field: NP (tensor basis) or the total-degree count
     long long ncells;
     dgk::Phys ph;
     dgk::Geo geo;
@@ -360,7 +377,8 @@ struct dg_ctx {
     double cfl;
     int device;
     bool grad;
-    int phys;    // 0 Euler, 1 Navier-Stokes, 2 artificial viscosity, 3 Navier-Stokes + tracer
+    int phys;    // 0 Euler, 1 Navier-Stokes, 2 artificial viscosity, 3 Navier-Stokes + tracer,
+                 // 4 / 5 Euler / Navier-Stokes on the total-degree basis
     KernelSet ks, ks64;
     const void *vol_fixed[2];   // fixed-tile volume kernels (no forcing / forcing) for the tile in use, or null
     const void *face_fixed;     // fixed-tile face kernel for the tile in use, or null
@@ -734,7 +752,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     if (opt) o = *opt;
     if (o.precision != DG_PREC_FP64 && o.precision != DG_PREC_FP32_BULK) return DG_EINVAL;
     if (o.tracer && (!(o.tracer_eta >= 0.0) || !std::isfinite(o.tracer_eta))) return DG_EINVAL;
-    if (o.basis != 0) return DG_EUNSUPPORTED;
+    if (o.basis != 0 && o.basis != 1) return DG_EINVAL;
     if (!(o.cfl > 0.0) || o.cells_per_block < 0 || o.faces_per_block < 0) return DG_EINVAL;
     if (o.vol_threads < 0 || o.vol_threads > 512 || o.vol_threads % 64 || o.face_threads < 0 ||
         o.face_threads > 512 || o.face_threads % 64)
@@ -756,6 +774,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     }
     const bool av_on = av && av->enabled;
     if (av_on && o.tracer) return DG_EUNSUPPORTED;   // no AV variant carries the tracer
+    if (o.basis == 1 && (av_on || o.tracer)) return DG_EUNSUPPORTED;   // P_n: Euler and Navier-Stokes
     if (av_on && (!(av->f_tau > 0.0) || !(av->alpha_max >= 0.0) || !(av->scale >= 0.0) || !(av->f_v >= 0.0) ||
                   !(av->f_w >= 0.0) || !(av->s_onset >= 0.0)))
         return DG_EINVAL;
@@ -776,6 +795,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     c->NP = 1;
     for (int a = 0; a < d; ++a) c->NP *= order;
     c->K = c->NP / order;
+    c->NM = o.basis == 0 ? c->NP : (d == 2 ? order * (order + 1) / 2 : order * (order + 1) * (order + 2) / 6);
     c->device = dev;
     c->precision = o.precision;
     c->cfl = o.cfl;
@@ -829,6 +849,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     }
     c->grad = ph.ns_on || ph.av_on;
     c->phys = ph.av_on ? 2 : (o.tracer ? 3 : (ph.ns_on ? 1 : 0));
+    if (o.basis == 1) c->phys = ph.ns_on ? 5 : 4;
     get_kernels(d, c->precision, order, c->phys, &c->ks);
     get_kernels(d, DG_PREC_FP64, order, c->phys, &c->ks64);
     if (!c->ks.vol || !c->ks.face || !c->ks64.cfl) {
@@ -919,7 +940,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     (void)set_lds(c->ks64.cfl, lim);
 
     // buffers
-    const size_t nstate = (size_t)c->ncells * c->F * c->NP;
+    const size_t nstate = (size_t)c->ncells * c->F * c->NM;
     const int nreg = c->stages == 1 ? 0 : c->stages == 2 ? 1 : c->stages == 3 ? 2 : 3;
     bool good = true;
     for (int i = 0; i < nreg && good; ++i) good = ok(hipMalloc(&c->reg[i], nstate * sizeof(double)));
@@ -1016,7 +1037,9 @@ dg_status dg_timing_read(dg_ctx *c, double *face_ms, long long *face_n, double *
     return DG_OK;
 }
 
-size_t dg_state_len(const dg_ctx *c) { return c ? (size_t)c->ncells * c->F * c->NP : 0; }
+size_t dg_state_len(const dg_ctx *c) { return c ? (size_t)c->ncells * c->F * c->NM : 0; }
+
+int dg_num_modes(const dg_ctx *c) { return c ? c->NM : 0; }
 
 int dg_num_fields(const dg_ctx *c) { return c ? c->F : 0; }
 
@@ -1132,7 +1155,7 @@ dg_status dg_conserved_totals(dg_ctx *c, const double *w, double *out, void *str
     for (int a = 0; a < c->dim; ++a) vol *= c->ph.h;
     {
         long long nc = c->ncells;
-        int F = c->F, NP = c->NP, Fc = c->Fc, chunk = c->tot_chunk;
+        int F = c->F, NP = c->NM, Fc = c->Fc, chunk = c->tot_chunk;
         double *part = c->tot_part;
         void *a1[] = {(void *)&w, &nc, &F, &NP, &Fc, &vol, &chunk, &part};
         if (!ok(hipLaunchKernel((const void *)&totals_partial, dim3(c->tot_blocks), dim3(256), a1, 0, s)))
@@ -1345,7 +1368,7 @@ static dg_status batch_init_impl(int nbox, const dg_mesh *meshes, const int *ord
     *out = nullptr;
     if (nbox < 1 || !meshes || !orders) return DG_EINVAL;
     if (av && av->enabled) return DG_EUNSUPPORTED;
-    if (opt && (opt->limiter || opt->tracer)) return DG_EUNSUPPORTED;
+    if (opt && (opt->limiter || opt->tracer || opt->basis)) return DG_EUNSUPPORTED;
     for (int i = 0; i < nbox; ++i)
         if (meshes[i].dim != meshes[0].dim) return DG_EINVAL;
     dg_batch *b = new (std::nothrow) dg_batch;

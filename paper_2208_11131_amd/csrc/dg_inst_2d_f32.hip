@@ -1,6 +1,7 @@
 // Kernel instantiations: dim = 2, bulk precision float, orders 1..8,
 // physics variants Euler / Navier-Stokes / artificial viscosity /
-// Navier-Stokes with the passive tracer.
+// Navier-Stokes with the passive tracer, and Euler / Navier-Stokes on the
+// total-degree basis.
 #include "dg_kernels.hpp"
 #include "dg_registry.hpp"
 
@@ -32,8 +33,12 @@ void pick(int ph, KernelSet *k)
         fill<P, 1>(k);
     else if (ph == 2)
         fill<P, 2>(k);
-    else
+    else if (ph == 3)
         fill<P, 3>(k);
+    else if (ph == 4)
+        fill<P, 4>(k);
+    else
+        fill<P, 5>(k);
 }
 }  // namespace
 

@@ -247,16 +247,44 @@ __device__ __forceinline__ void dt_lift_pass(const T *__restrict__ in, T *__rest
 
 // Fields per physics variant: PH = 0 Euler, 1 Navier-Stokes, 2 artificial
 // viscosity (alpha field; Navier-Stokes terms switched at run time),
-// 3 Navier-Stokes with the passive tracer c rho (Sec. 3.4).  Fc conserved
-// fields carry face fluxes: the D + 2 hydro fields and the tracer.
+// 3 Navier-Stokes with the passive tracer c rho (Sec. 3.4); PH = 4 / 5 are
+// Euler / Navier-Stokes on the total-degree basis P_n (Sec. 2.3).  Fc
+// conserved fields carry face fluxes: the D + 2 hydro fields and the tracer.
 template <int D, int PH>
 struct Fld {
+    static constexpr bool PN = PH >= 4;
+    static constexpr int BASE = PN ? PH - 4 : PH;
     static constexpr int NH = D + 2;
-    static constexpr bool TR = PH == 3;
+    static constexpr bool TR = BASE == 3;
+    static constexpr bool AV = BASE == 2;
     static constexpr int Fc = NH + (TR ? 1 : 0);
-    static constexpr int F = Fc + (PH == 2 ? 1 : 0);
-    static constexpr bool GRAD = PH > 0;
-    static constexpr bool NS = PH == 1 || PH == 3;   // Navier-Stokes terms compiled in
+    static constexpr int F = Fc + (AV ? 1 : 0);
+    static constexpr bool GRAD = BASE > 0;
+    static constexpr bool NS = BASE == 1 || BASE == 3;   // Navier-Stokes terms compiled in
+};
+
+// Storage of one field's modal weights.  Q_n: the p^d tensor modes, index
+// l_x + p (l_y + p l_z).  P_n: the modes of total degree <= n = p - 1 in the
+// order l_z, l_y, l_x ascending (l_x fastest): the "line" of transverse
+// digits (l_y, l_z) holds l_x = 0 .. n - l_y - l_z contiguously from
+// off(l_y, l_z) = Tet(p) - Tet(p - l_z) + l_y (p - l_z) - l_y (l_y - 1)/2,
+// Tet(q) = q (q+1) (q+2) / 6.  Kernels expand a cell to the tensor layout in
+// registers / LDS (absent modes are 0) and store back only the P_n modes.
+template <int D, int P, bool PN>
+struct Basis {
+    static constexpr int NM = PN ? (D == 2 ? P * (P + 1) / 2 : P * (P + 1) * (P + 2) / 6) : ipow(P, D);
+    static __host__ __device__ constexpr int tet(int q) { return q * (q + 1) * (q + 2) / 6; }
+    // start and length of the l_x line with transverse digits (ly, lz)
+    static __device__ __forceinline__ int off(int ly, int lz)
+    {
+        return PN ? tet(P) - tet(P - lz) + ly * (P - lz) - ly * (ly - 1) / 2 : (ly + P * lz) * P;
+    }
+    static __device__ __forceinline__ int len(int ly, int lz) { return PN ? (P - ly - lz > 0 ? P - ly - lz : 0) : P; }
+    // storage index of mode (lx, ly, lz), -1 if it is not in the basis
+    static __device__ __forceinline__ int idx(int lx, int ly, int lz)
+    {
+        return (PN && lx + ly + lz > P - 1) ? -1 : off(ly, lz) + lx;
+    }
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
@@ -422,7 +450,10 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     constexpr int Fc = Fld<D, PH>::Fc;
     constexpr int F = Fld<D, PH>::F;
     constexpr bool GRAD = Fld<D, PH>::GRAD;
-    constexpr int FNP = F * NP;
+    constexpr bool PN = Fld<D, PH>::PN;
+    using BS = Basis<D, P, PN>;
+    constexpr int NM = BS::NM;         // stored modes per field
+    constexpr int FNP = F * NM;        // stored weights per cell
     constexpr int NA = GRAD ? 4 : 2;
     constexpr int S = ipow(P, AX);
     constexpr int PP = FacePad<P>::PP;
@@ -497,12 +528,26 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
             const int t = q - sf * K;
             const int sl = sf / F, f = sf - sl * F;
             const int lo = t % S, hi = t / S;
-            const double *src = a.w + cellidx[sl] * FNP + f * NP + lo + hi * S * P;
+            const double *src = a.w + cellidx[sl] * FNP + f * NM + lo + hi * S * P;
             const int mk = mir[sl];
             const bool mr = mk != 0;                       // odd modes negated
             const bool wn = mk == 2 && f == 1 + AX;        // wall: normal momentum negated
             T x[P];
-            if (AX == 0 && P % 2 == 0) {
+            // P_n: the line's recovery vectors belong to its transverse degree
+            // tau (data of normal degree <= n - tau recovered to n + 1 - tau)
+            int tau = 0;
+            if constexpr (PN) {
+                const int t0 = lo + hi * S * P;            // tensor index of normal digit 0
+                tau = t0 % P + (t0 / P) % P + t0 / (P * P);
+                const double *cp = a.w + cellidx[sl] * FNP + f * NM;
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    const int ti = t0 + m * S;
+                    const int id = BS::idx(ti % P, (ti / P) % P, ti / (P * P));
+                    const double v = id >= 0 ? cp[id] : 0.0;
+                    x[m] = (T)(((mr && (m & 1)) != wn) ? -v : v);
+                }
+            } else if (AX == 0 && P % 2 == 0) {
 #pragma unroll
                 for (int m = 0; m < P; m += 2) {
                     const DV<2> v = ldv<2>(src + m);
@@ -524,11 +569,12 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                 for (int m = 0; m < P; ++m) tl = fma(tb.ep[m], x[m], tl);
                 A[0 * Q + qa] = tl;
                 if (GRAD) {
+                    const T *vL = PN ? tb.prvL[tau] : tb.rvL, *dL = PN ? tb.prdL[tau] : tb.rdL;
                     T rv = T(0), rn = T(0);
 #pragma unroll
                     for (int m = 0; m < P; ++m) {
-                        rv = fma(tb.rvL[m], x[m], rv);
-                        rn = fma(tb.rdL[m], x[m], rn);
+                        rv = fma(vL[m], x[m], rv);
+                        rn = fma(dL[m], x[m], rn);
                     }
                     A[2 * Q + qa] = rv;
                     A[3 * Q + qa] = rn;
@@ -541,11 +587,12 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                 for (int m = 0; m < P; ++m) tr = fma(tb.em[m], x[m], tr);
                 A[1 * Q + qa] = tr;
                 if (GRAD) {
+                    const T *vR = PN ? tb.prvR[tau] : tb.rvR, *dR = PN ? tb.prdR[tau] : tb.rdR;
                     T rv = T(0), rn = T(0);
 #pragma unroll
                     for (int m = 0; m < P; ++m) {
-                        rv = fma(tb.rvR[m], x[m], rv);
-                        rn = fma(tb.rdR[m], x[m], rn);
+                        rv = fma(vR[m], x[m], rv);
+                        rn = fma(dR[m], x[m], rn);
                     }
                     A2u[qa] = rv;
                     A3u[qa] = rn;
@@ -623,7 +670,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
             // tracer diffusion eta rho d_a c = eta (d_a(c rho) - c d_a rho)
             if (Fld<D, PH>::TR) vis[D + 2] = (T)ph.eta * (g[AX][D + 2] - ut[D + 2] * s.ir * g[AX][0]);
         }
-        if (PH == 2) {
+        if (Fld<D, PH>::AV) {
             const T cs = sqrt(gamma * s.p * s.ir);
             const T eps = (T)ph.av_scale * clamp_alpha(ut[Fc], (T)ph.alpha_max) * cs * (T)ph.eps_fac;
 #pragma unroll
@@ -828,6 +875,34 @@ size_t face_lds_bytes(int C)
     return hdr + sizeof(T) * tot;
 }
 
+// Sensor top modes (Sec. 4.1: absent at the next lower order) by storage
+// index: max_a l_a = n for Q_n, total degree n for P_n.
+template <int D, int P, bool PN>
+__device__ __forceinline__ bool is_top(int m)
+{
+    if constexpr (PN) {
+        // walk the P_n storage order to the degrees of m
+        int lz = 0, ly = 0;
+        while (true) {
+            const int nl = Basis<D, P, true>::len(ly, lz);
+            if (m < nl) return m + ly + lz == P - 1;
+            m -= nl;
+            if (++ly > P - 1 - lz) {
+                ly = 0;
+                ++lz;
+            }
+        }
+    } else {
+        bool tp = false;
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            tp = tp || (m % P == P - 1);
+            m /= P;
+        }
+        return tp;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // volume kernel
 // ---------------------------------------------------------------------------
@@ -861,7 +936,10 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     constexpr int Fc = Fld<D, PH>::Fc;
     constexpr int F = Fld<D, PH>::F;
     constexpr bool GRAD = Fld<D, PH>::GRAD;
-    constexpr int FNP = F * NP;
+    constexpr bool PN = Fld<D, PH>::PN;
+    using BS = Basis<D, P, PN>;
+    constexpr int NM = BS::NM;                // stored modes per field
+    constexpr int FNP = F * NM;               // stored weights per cell
     const bool forced = FO >= 0 ? FO == 1 : a.forcing != nullptr;
     const int Fx = F + (forced ? D : 0);
     const int C = CC > 0 ? CC : a.cells_per_block;
@@ -915,21 +993,14 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
             fidx[(cl * D + ax) * 2] = flo;
             fidx[(cl * D + ax) * 2 + 1] = fhi;
         }
-        if (PH == 2) {
+        if (Fld<D, PH>::AV) {
             // sensor S of the current state and the wiggle source (Sec. 4.1)
             const double *wr = a.cur + cc * FNP;
             double all = 0.0, top = 0.0;
-            for (int m = 0; m < NP; ++m) {
+            for (int m = 0; m < NM; ++m) {
                 const double x = wr[m];
                 all += x * x;
-                bool tp = false;
-                int r = m;
-#pragma unroll
-                for (int b = 0; b < D; ++b) {
-                    tp = tp || (r % P == P - 1);
-                    r /= P;
-                }
-                if (tp) top += x * x;
+                if (is_top<D, P, PN>(m)) top += x * x;
             }
             const double Sv = all > 0.0 ? top / all : 0.0;
             const double Rp = a.R_prev ? a.R_prev[cc] : 0.0;
@@ -959,7 +1030,15 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
             long long cc = c0 + c;
             if (cc >= NC) cc = NC - 1;                  // tail cells: copies of the last cell
             T x[P];
-            if (f < F) {
+            if constexpr (PN) {
+                // the line's l_x modes (zeros above total degree n)
+                const int ly = t % P, lz = t / P;
+                const int o0 = BS::off(ly, lz), nl = BS::len(ly, lz);
+                const double *src = f < F ? a.cur + cc * FNP + f * NM + o0
+                                          : a.forcing + cc * (D * NM) + (f - F) * NM + o0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) x[k] = (T)(k < nl ? src[k] : 0.0);
+            } else if (f < F) {
                 const double *src = a.cur + cc * FNP + f * NP + t * P;
 #pragma unroll
                 for (int k = 0; k < P; k += VWL) {
@@ -1035,7 +1114,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
                 for (int f = 0; f < F; ++f) g[b][f] = G[(b * F + f) * CNP + q] * (T)ph.two_over_h;
         }
         T eps = T(0), cs = T(0);
-        if (PH == 2) {
+        if (Fld<D, PH>::AV) {
             cs = sqrt(gamma * s.p * s.ir);
             eps = (T)ph.av_scale * clamp_alpha(u[Fc], (T)ph.alpha_max) * cs * (T)ph.eps_fac;
         }
@@ -1046,14 +1125,14 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
             T fl[Fc];
             euler_flux<D, T>(u, s, b, fl);
             if (Fld<D, PH>::TR) fl[D + 2] = u[D + 2] * s.v[b];
-            if (Fld<D, PH>::NS || (PH == 2 && ph.ns_on)) {
+            if (Fld<D, PH>::NS || (Fld<D, PH>::AV && ph.ns_on)) {
                 T fv[D + 2];
                 ns_flux<D, T>(s, ng, b, gamma, (T)ph.nu, (T)ph.kappa, fv);
 #pragma unroll
                 for (int f = 0; f < D + 2; ++f) fl[f] -= fv[f];
                 if (Fld<D, PH>::TR) fl[D + 2] -= (T)ph.eta * (g[b][D + 2] - u[D + 2] * s.ir * g[b][0]);
             }
-            if (PH == 2) {
+            if (Fld<D, PH>::AV) {
 #pragma unroll
                 for (int f = 0; f < Fc; ++f) fl[f] -= eps * g[b][f];
             }
@@ -1076,7 +1155,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         }
 #pragma unroll
         for (int f = 0; f < Fc; ++f) U[f * CNP + q] = hw * src[f];
-        if (PH == 2) {
+        if (Fld<D, PH>::AV) {
             const T asrc = (T)ph.f_v * fmax(T(0), -ng.div) + (T)cellv[cq] - u[Fc] * cs * (T)ph.sink;
             U[Fc * CNP + q] = hw * asrc;
         }
@@ -1162,6 +1241,19 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         const int f = arr / C, c = arr - f * C;
         const long long cc = c0 + c;
         const bool ok = q < nx && cc < NC;
+        if constexpr (PN) {
+            const int ly = t % P, lz = t / P;
+            const long long gi = cc * FNP + f * NM + BS::off(ly, lz);
+            const int nl = BS::len(ly, lz);
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const bool in = ok && k < nl;
+                if (with_cur) cu[k] = in ? a.cur[gi + k] : 0.0;
+                ba[k] = (in && a.base) ? a.base[gi + k] : 0.0;
+                x2[k] = (in && a.x2) ? a.x2[gi + k] : 0.0;
+            }
+            return;
+        }
         const long long gi = cc * FNP + f * NP + t * P;
 #pragma unroll
         for (int k = 0; k < P; k += VWL) {
@@ -1271,12 +1363,15 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
             for (int k = 0; k < K; ++k) y0 += m0s[arr * K + k];
             y[0] = (T)y0;
         }
-        if (PH == 2) {
+        if (Fld<D, PH>::AV) {
 #pragma unroll
             for (int i = 0; i < P; ++i) Vl[o + i] = y[i];
         }
         if (cc >= NC) return;
-        const long long gi = cc * FNP + f * NP + t * P;
+        // stored weights of this line: all p (Q_n), the first len (P_n)
+        const int ly = t % P, lz = t / P;
+        const int nl = BS::len(ly, lz);
+        const long long gi = PN ? cc * FNP + f * NM + BS::off(ly, lz) : cc * FNP + f * NP + t * P;
         double ov[P], o2v[P];
 #pragma unroll
         for (int i = 0; i < P; ++i) {
@@ -1284,7 +1379,17 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
             ov[i] = a.c_cur * cu[i] + a.c_L * dt * L;
             if (a.base) ov[i] += a.c_base * ba[i];
             o2v[i] = a.d_cur * cu[i] + a.d_L * dt * L + (a.x2 ? a.d_x2 * x2[i] : 0.0);
-            if (!isfinite(ov[i])) bad |= 2;
+            if (!isfinite(ov[i]) && i < nl) bad |= 2;
+        }
+        if constexpr (PN) {
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                if (i < nl) {
+                    if (a.out2) a.out2[gi + i] = o2v[i];
+                    a.out[gi + i] = ov[i];
+                }
+            if (t == 0 && f < D + 2) cmean[c * (D + 2) + f] = ov[0];
+            return;
         }
 #pragma unroll
         for (int k = 0; k < P; k += VWL) {
@@ -1320,7 +1425,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         for (int i = 0; i < D; ++i) m2 += o[1 + i] * o[1 + i];
         const double pm = (ph.gamma - 1.0) * (o[D + 1] - 0.5 * m2 / rho);
         if (a.check && !(rho > 0.0 && pm > 0.0)) atomicOr(blkflag, 1);
-        if (PH == 2 && a.R_out) {
+        if constexpr (Fld<D, PH>::AV) if (a.R_out) {
             const double *wr = a.cur + cc * FNP;
             double Aa = 0.0, Tt = 0.0, ad = 0.0, td = 0.0;
             for (int m = 0; m < NP; ++m) {
@@ -1446,7 +1551,9 @@ __device__ __forceinline__ void cfl_tile(const Phys &ph, const Geo &geo, const C
 {
     constexpr int NP = ipow(P, D);
     constexpr int Fc = D + 2;
-    constexpr int FNP = Fld<D, PH>::F * NP;
+    constexpr bool PN = Fld<D, PH>::PN;
+    using BS = Basis<D, P, PN>;
+    constexpr int FNP = Fld<D, PH>::F * BS::NM;
     const int C = a.cells_per_block;
     const int tid = threadIdx.x, nt = blockDim.x;
     const long long NC = geo.ncells;
@@ -1466,13 +1573,21 @@ __device__ __forceinline__ void cfl_tile(const Phys &ph, const Geo &geo, const C
             const int f = arr / C, c = arr - f * C;
             long long cc = c0 + c;
             if (cc >= NC) cc = NC - 1;
-            const double *src = a.w + cc * FNP + f * NP + t * P;
             double x[P];
+            if constexpr (PN) {
+                const int ly = t % P, lz = t / P;
+                const double *src = a.w + cc * FNP + f * BS::NM + BS::off(ly, lz);
+                const int nl = BS::len(ly, lz);
 #pragma unroll
-            for (int k = 0; k < P; k += VWL) {
-                const DV<VWL> v = ldv<VWL>(src + k);
+                for (int k = 0; k < P; ++k) x[k] = k < nl ? src[k] : 0.0;
+            } else {
+                const double *src = a.w + cc * FNP + f * NP + t * P;
 #pragma unroll
-                for (int h = 0; h < VWL; ++h) x[k + h] = v.x[h];
+                for (int k = 0; k < P; k += VWL) {
+                    const DV<VWL> v = ldv<VWL>(src + k);
+#pragma unroll
+                    for (int h = 0; h < VWL; ++h) x[k + h] = v.x[h];
+                }
             }
             const int o = pad_line_offset<P, D, 0>(q);
 #pragma unroll
@@ -1619,7 +1734,10 @@ __device__ __forceinline__ void limit_tile(const Phys &ph, const Geo &geo, doubl
     constexpr int E = LimGeo<D, P>::E, NE = LimGeo<D, P>::NE, Fc = D + 2;
     constexpr int NP = ipow(P, D);
     constexpr int F = Fld<D, PH>::F;
-    constexpr int FNP = F * NP;
+    constexpr bool PN = Fld<D, PH>::PN;
+    using BS = Basis<D, P, PN>;
+    constexpr int NM = BS::NM;
+    constexpr int FNP = F * NM;
     const Tab<double> &tb = TabSel<double>::get(P);
     const int tid = threadIdx.x, nt = blockDim.x;
     const long long NC = geo.ncells;
@@ -1639,10 +1757,12 @@ __device__ __forceinline__ void limit_tile(const Phys &ph, const Geo &geo, doubl
         const int f = arr / C, c = arr - f * C;
         long long cc = c0 + c;
         if (cc >= NC) cc = NC - 1;
-        const double *src = w + cc * FNP + f * NP + t * P;
+        const int ly = t % P, lz = t / P;
+        const double *src = w + cc * FNP + f * NM + BS::off(ly, lz);
+        const int nl = BS::len(ly, lz);
         double x[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = src[k];
+        for (int k = 0; k < P; ++k) x[k] = k < nl ? src[k] : 0.0;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             double acc = 0.0;
@@ -1709,7 +1829,7 @@ __device__ __forceinline__ void limit_tile(const Phys &ph, const Geo &geo, doubl
         long long cc = c0 + c;
         if (cc >= NC) cc = NC - 1;
 #pragma unroll
-        for (int f = 0; f < Fc; ++f) um[f] = w[cc * FNP + f * NP];
+        for (int f = 0; f < Fc; ++f) um[f] = w[cc * FNP + f * NM];
     };
     // minimum in which NaN counts as lower than anything (a NaN pressure must
     // be limited)
@@ -1791,9 +1911,9 @@ __device__ __forceinline__ void limit_tile(const Phys &ph, const Geo &geo, doubl
         if (!more) break;
     }
     // write the limited cells: weights of degree >= 1 of every field
-    for (int q = tid; q < C * F * NP; q += nt) {
-        const int c = q / (F * NP), r = q - c * (F * NP);
-        if (r % NP == 0) continue;                   // the mean
+    for (int q = tid; q < C * F * NM; q += nt) {
+        const int c = q / (F * NM), r = q - c * (F * NM);
+        if (r % NM == 0) continue;                   // the mean
         const double th = theta[c];
         const long long cc = c0 + c;
         if (th < 1.0 && cc < NC) w[cc * FNP + r] *= th;
