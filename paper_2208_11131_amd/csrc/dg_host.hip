@@ -1255,6 +1255,12 @@ struct dg_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;     // private stream for graph capture
+    // independent units (each large box, each order group) run on their own
+    // streams, forked from and joined back to the step's stream: parallel
+    // branches of the captured graph
+    std::vector<hipStream_t> ustream;
+    std::vector<hipEvent_t> uevent;
+    hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -1264,6 +1270,11 @@ void batch_release(dg_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (hipStream_t st : b->ustream)
+        if (st) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : b->uevent)
+        if (e) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     for (Group &g : b->groups)
         if (g.d_desc) (void)hipFree(g.d_desc);
     for (dg_ctx *c : b->box) dg_free(c);
@@ -1319,16 +1330,23 @@ int stage_table(int S, dgk::StageDesc *sd)
 // kernels' per-block box lookup only pays off for the small, launch-bound ones.
 constexpr long long kBatchLargeCells = 65536;
 
-dg_status batch_enqueue(dg_batch *b, hipStream_t s)
+// Streams over which the independent units of a batched step are spread.
+constexpr int kBatchStreams = 8;
+
+// The step of one unit: a large box (its own kernels) or an order group
+// (grouped launches over its boxes), all on stream s.
+dg_status unit_enqueue(dg_batch *b, int u, hipStream_t s)
 {
-    for (int i : b->large) {
+    if (u < (int)b->large.size()) {
+        const int i = b->large[u];
         dg_ctx *c = b->box[i];
         dg_status st = run_cfl(c, b->wptr[i], nullptr, s, false);
         if (st == DG_OK) st = rk_step(c, b->wptr[i], 0.0, c->scal, s);
         c->fin_pending = false;
-        if (st != DG_OK) return st;
+        return st;
     }
-    for (Group &g : b->groups) {
+    {
+        Group &g = b->groups[u - b->large.size()];
         const int n = (int)g.boxes.size();
         dgk::BoxDesc *d = g.d_desc;
         {
@@ -1353,6 +1371,34 @@ dg_status batch_enqueue(dg_batch *b, hipStream_t s)
             if (!ok(hipLaunchKernel(g.ks.vol_b, dim3((unsigned)g.nblk[0]), dim3(g.vol_T), vargs, g.vol_lds, s)))
                 return DG_EDEVICE;
         }
+    }
+    return DG_OK;
+}
+
+// The whole batched step on stream s: every unit on its own stream (round
+// robin over the batch's streams), forked from s by an event and joined back
+// by one event per unit, so that independent boxes overlap on the device.
+dg_status batch_enqueue(dg_batch *b, hipStream_t s)
+{
+    const int nu = (int)(b->large.size() + b->groups.size());
+    const int ns = (int)b->ustream.size();
+    if (ns == 0) {
+        for (int u = 0; u < nu; ++u) {
+            dg_status st = unit_enqueue(b, u, s);
+            if (st != DG_OK) return st;
+        }
+        return DG_OK;
+    }
+    if (!ok(hipEventRecord(b->fork, s))) return DG_EDEVICE;
+    for (int k = 0; k < ns; ++k)
+        if (!ok(hipStreamWaitEvent(b->ustream[k], b->fork, 0))) return DG_EDEVICE;
+    for (int u = 0; u < nu; ++u) {
+        dg_status st = unit_enqueue(b, u, b->ustream[u % ns]);
+        if (st != DG_OK) return st;
+    }
+    for (int k = 0; k < ns; ++k) {
+        if (!ok(hipEventRecord(b->uevent[k], b->ustream[k]))) return DG_EDEVICE;
+        if (!ok(hipStreamWaitEvent(s, b->uevent[k], 0))) return DG_EDEVICE;
     }
     return DG_OK;
 }
@@ -1466,6 +1512,22 @@ static dg_status batch_init_impl(int nbox, const dg_mesh *meshes, const int *ord
             gb.d_desc = nullptr;
             (void)hipGetLastError();
             return DG_ENOMEM;
+        }
+    }
+    // streams for the independent units (default priority, non-blocking)
+    {
+        const int nu = (int)(b->large.size() + b->groups.size());
+        const int ns = std::min(nu, kBatchStreams);
+        if (ns > 1) {
+            if (!ok(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming))) return DG_EDEVICE;
+            for (int k = 0; k < ns; ++k) {
+                hipStream_t st = nullptr;
+                hipEvent_t ev = nullptr;
+                if (!ok(hipStreamCreateWithFlags(&st, hipStreamNonBlocking))) return DG_EDEVICE;
+                b->ustream.push_back(st);
+                if (!ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming))) return DG_EDEVICE;
+                b->uevent.push_back(ev);
+            }
         }
     }
     guard.b = nullptr;
