@@ -35,6 +35,8 @@ Extra objects on the JSON line:
   kh_2d        the 2D shear layer, 256 x 512, p = 4 (FP64 and FP32 bulk);
   sod_av_2d    the AV shock tube, 1024 x 128, p = 6 (Euler + artificial
                viscosity, reflecting walls at the x ends), FP64;
+  turbulence_3d_pn  the headline box on the total-degree basis P_n (20 modes
+               per field at p = 4 instead of 64; Sec. 2.3), same driving;
   ensemble     48 independent 2D boxes (sides 32..512, orders 2..6) stepped by
                one captured hipGraph (grouped launches for the small boxes),
                against the same steps issued box by box;
@@ -134,11 +136,18 @@ def make_workload(name, order, device, precision):
         desc = {"workload": "kelvin_helmholtz_2d", "cells": [nx, ny], "order": order, "fields": 4,
                 "physics": "navier_stokes nu=kappa=1e-4", "gamma": 5.0 / 3.0}
         return s, w, None, desc, dict(dim=2, ns=True, av=False)
-    if name == "turb":
+    if name in ("turb", "turb_pn"):
         n = 128
+        basis = 1 if name == "turb_pn" else 0
         w, _ = W.turbulence(order, n, device=device)
-        s = dg.Solver(3, (n, n, n), order, 1.0001, nu=2e-5, kappa=2e-5, precision=precision, cfl=0.5)
-        drv = dg.Driving(3, (n, n, n), order, kmax=3, t_corr=1.0, sigma0=0.5)
+        if basis == 1:
+            # the same initial field restricted to total degree <= n, in the P_n storage order
+            keep = [lx + order * (ly + order * lz) for lz in range(order) for ly in range(order - lz)
+                    for lx in range(order - ly - lz)]
+            w = w[:, :, keep].contiguous()
+        s = dg.Solver(3, (n, n, n), order, 1.0001, nu=2e-5, kappa=2e-5, precision=precision, cfl=0.5,
+                      basis=basis)
+        drv = dg.Driving(3, (n, n, n), order, kmax=3, t_corr=1.0, sigma0=0.5, basis=basis)
         f = torch.empty(s.ncells * 3 * s.nmodes, dtype=torch.float64, device=device)
         noise = W.ou_noise(drv.nm, 1024, seed=2208)
         drv.update(noise[0], math.inf)                       # stationary start
@@ -153,8 +162,9 @@ def make_workload(name, order, device, precision):
                 drv.update(noise[state["k"] % len(noise)], every * dt0)
                 state["k"] += 1
                 drv.project(f)
-        desc = {"workload": "driven_turbulence_3d", "cells": [n, n, n], "order": order, "fields": 5,
-                "physics": "navier_stokes nu=kappa=2e-5 + OU driving", "gamma": 1.0001,
+        desc = {"workload": "driven_turbulence_3d" + ("_pn" if basis else ""), "cells": [n, n, n], "order": order,
+                "fields": 5, "basis": "P_n (total degree)" if basis else "Q_n (tensor)",
+                "modes": s.nmodes, "physics": "navier_stokes nu=kappa=2e-5 + OU driving", "gamma": 1.0001,
                 "driving": "OU modes 1<=|k|<=3, update + projection every %d steps" % every}
         return s, w, f, desc, dict(dim=3, ns=True, av=False, refresh=refresh, keep=drv)
     if name == "sod":
@@ -414,7 +424,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--repeats", type=int, default=5)
-    ap.add_argument("--config", default="turb", choices=["kh", "turb", "sod"])
+    ap.add_argument("--config", default="turb", choices=["kh", "turb", "turb_pn", "sod"])
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -486,6 +496,15 @@ def main():
         line["fp32_bulk"] = rec
         del r32
         torch.cuda.empty_cache()
+        if name == "turb":
+            print("bench: total-degree basis", file=sys.stderr, flush=True)
+            rp = measure("turb_pn", order, "fp64", 10, 3, 3)
+            line["turbulence_3d_pn"] = {"value": rp["value"], "ms_per_step": rp["ms"] / 10, "config": rp["desc"],
+                                        "dofs": rp["dofs"], "step_time_vs_tensor_basis": rp["ms"] / 10 /
+                                        line["ms_per_step"], "roofline": kernel_record(rp),
+                                        "stage_roofline": rp["stage"]}
+            del rp
+            torch.cuda.empty_cache()
         if name != "kh":
             print("bench: 2D shear layer", file=sys.stderr, flush=True)
             rk = measure("kh", 4, "fp64", 20, 60, 3)

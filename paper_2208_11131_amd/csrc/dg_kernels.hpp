@@ -1937,7 +1937,7 @@ template <int DIM, int PREC, typename T, size_t I, int FO>
 FixedVol fixed_vol_entry()
 {
     constexpr TileEntry e = kTiles[I];
-    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 2 &&
+    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 5 &&
                   e.vol_C > 0 && e.vol_T >= 64 && e.vol_T <= 512 && e.vol_T % 64 == 0 && (FO == 0 || DIM == 3))
         return FixedVol{e.order, e.phys, e.vol_C, e.vol_T, FO,
                         (const void *)&vol_kernel_fixed<DIM, e.order, T, e.phys, e.vol_C, e.vol_T, FO>,
@@ -1952,7 +1952,7 @@ template <int DIM, int PREC, typename T, size_t I>
 FixedVol fixed_face_entry()
 {
     constexpr TileEntry e = kTiles[I];
-    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 2 &&
+    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 5 &&
                   e.face_C > 0 && e.face_T >= 64 && e.face_T <= 512 && e.face_T % 64 == 0)
         return FixedVol{e.order, e.phys, e.face_C, e.face_T, 0,
                         (const void *)&face_kernel_fixed<DIM, e.order, T, e.phys, e.face_C, e.face_T>,

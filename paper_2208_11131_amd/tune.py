@@ -25,7 +25,8 @@ from . import workloads as W
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 # (dim, order, precision, physics) configurations of the workloads
-#   physics: 0 Euler, 1 Navier-Stokes, 2 artificial viscosity
+#   physics: 0 Euler, 1 Navier-Stokes, 2 artificial viscosity (3 tracer, 4 / 5 total-degree
+#   basis: not tuned here; their rows in dg_tiles.inc are kept by hand)
 CONFIGS = ([(2, p, pr, 1) for p in range(2, 9) for pr in (0, 1)] +        # shear layer
            [(2, 6, pr, 2) for pr in (0, 1)] +                             # shock tube
            [(3, 4, pr, 1) for pr in (0, 1)] +                             # 3D turbulence
