@@ -4,12 +4,15 @@
  * The library evaluates the right-hand side of the DG weight equations of
  * Cernetic, Springel, Guillet & Pakmor (arXiv 2208.11131) for the compressible
  * Euler / Navier-Stokes equations on a uniform Cartesian mesh of cubic cells
- * with a per-cell tensor-product Legendre basis, and advances them with SSP
- * Runge-Kutta steps under a CFL time step.
+ * with a per-cell Legendre basis (the tensor set Q_n or the total-degree set
+ * P_n of Sec. 2.3), and advances them with SSP Runge-Kutta steps under a CFL
+ * time step; with it come the positivity limiter (Sec. 4.2), the passive
+ * tracer (Sec. 3.4) and the Ornstein-Uhlenbeck driving field (Sec. 7.1).
  *
  * Conventions shared by every call:
  *   - Order p (the `order` argument) = n + 1 = modes = Gauss points per axis,
- *     1 <= p <= 8 (Sec. 2.3, 2.4).  Modes per field: p^dim (tensor set Q_n).
+ *     1 <= p <= 8 (Sec. 2.3, 2.4).  Modes per field: p^dim (tensor set Q_n)
+ *     or p(p+1)/2, p(p+1)(p+2)/6 in 2D, 3D (total-degree set P_n).
  *   - State layout (device, float64, C-contiguous): w[cell][field][mode],
  *     cell = i + n0 (j + n1 k), mode = l_x + p (l_y + p l_z) (tensor basis;
  *     the total-degree basis of dg_options.basis = 1 stores its modes as

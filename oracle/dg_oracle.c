@@ -24,8 +24,12 @@
  *                                                        timedependentviscosity,
  *                                                        viscosu_flux_with_factor)
  *   - SSP Runge-Kutta stepping and CFL time step        (Sec. 2.5, eq. timestep)
+ *   - passive tracer c rho                               (Sec. 3.4, eq. passivetracer)
+ *   - positivity limiter                                 (Sec. 4.2)
+ *   - Ornstein-Uhlenbeck driving field and its source   (Sec. 7.1)
  *
- * The basis is the full tensor-product set Q_n: (n+1)^d modes per field.
+ * The basis is the tensor set Q_n ((n+1)^d modes per field) or the
+ * total-degree set P_n (Sec. 2.3 eqs. N2D, N3D), chosen by or_params.basis.
  *
  * Readings taken where the paper is garbled or silent (each also listed in the
  * design notes of the repository):
@@ -46,7 +50,14 @@
  *   - epsilon uses clamp(alpha, 0, alpha_max); the stored alpha is unclamped;
  *   - RK: p=1 forward Euler, p=2 SSPRK(2,2), p=3 SSPRK(3,3), p>=4 SSPRK(5,4)
  *     of Spiteri & Ruuth (2002) in Shu-Osher form;
- *   - outflow boundary = mirrored ghost cell w_ghost(l_a) = (-1)^l_a w(l_a).
+ *   - outflow boundary = mirrored ghost cell w_ghost(l_a) = (-1)^l_a w(l_a);
+ *     reflecting wall = the same with the normal momentum negated;
+ *   - P_n recovery: the basis on K* of total degree <= n+1;
+ *   - limiter points: volume Gauss points and the Gauss points of the faces;
+ *     every higher weight of every field is scaled; rho_bottom = 1e-6 rho_bar,
+ *     p_bottom = 1e-6 p_bar, at most 60 halvings;
+ *   - driving field: amplitudes sigma0 |k|^(-5/3) on 1 <= |k| <= kmax, made
+ *     solenoidal after each OU update, given to the RHS as DG coefficients.
  *
  * Compile: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC
  */
