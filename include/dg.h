@@ -256,14 +256,17 @@ dg_status dg_forcing_set_amplitudes(dg_forcing *f, const double *amp);
 /* One OU step over dt > 0: every component becomes
  * e^{-dt/t_corr} a + sigma_k sqrt(1 - e^{-2 dt/t_corr}) (xi_re + i xi_im)/sqrt(2)
  * with the caller's standard normal draws noise[nm][3][2] (host), then the
- * solenoidal projection.  dt = +inf draws from the stationary law.  Host only. */
+ * solenoidal projection.  dt = +inf draws from the stationary law.  Host
+ * only; non-finite draws are rejected (DG_EINVAL, amplitudes unchanged). */
 dg_status dg_forcing_update(dg_forcing *f, const double *noise, double dt);
 /* DG coefficients of s on every cell, s_coeffs (device, caller-owned,
  * [cell][dim][modes] doubles): (1/|K|) int_K s phi_l, each mode's cell
  * integral factorised into per-axis factors (1/2) int exp(i pi k_a h xi)
  * Pt_l(xi) dxi tabulated on the host (modes in the layout of the basis).
  * Copies the amplitudes to the device
- * (synchronising `stream`), then enqueues one kernel. */
+ * (synchronising `stream`), then enqueues one kernel.  The device table is
+ * the object's own: calls on one object must not overlap on different
+ * streams. */
 dg_status dg_forcing_project(dg_forcing *f, double *s_coeffs, void *stream);
 
 /* Per-cell d ln S / dt used by the wiggle source (Sec. 4.1): copy from /

@@ -117,13 +117,29 @@ void build_static(dg_forcing *f)
 // tensor basis; for the total-degree basis the modes of degree <= p - 1 in
 // the order l_z, l_y, l_x ascending (l_x fastest).
 template <int D>
+__device__ __forceinline__ void project_item(const double *__restrict__ tab, int nm, int kmax, int P, int NP,
+                                             int basis, int n0, int n1, double lo0, double lo1, double lo2, double h,
+                                             long long item, double *__restrict__ s);
+
+// Grid-stride over the (cell, mode) items, so that any mesh fits a grid of
+// at most 2^20 blocks.
+template <int D>
 __global__ void __launch_bounds__(256) forcing_project_kernel(const double *__restrict__ tab, int nm, int kmax,
                                                               int P, int NP, int basis, int n0, int n1, double lo0,
                                                               double lo1, double lo2, double h, long long ncells,
                                                               double *__restrict__ s)
 {
-    const long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= ncells * NP) return;
+    const long long total = ncells * NP;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x; item < total; item += stride)
+        project_item<D>(tab, nm, kmax, P, NP, basis, n0, n1, lo0, lo1, lo2, h, item, s);
+}
+
+template <int D>
+__device__ __forceinline__ void project_item(const double *__restrict__ tab, int nm, int kmax, int P, int NP,
+                                             int basis, int n0, int n1, double lo0, double lo1, double lo2, double h,
+                                             long long item, double *__restrict__ s)
+{
     const long long cell = item / NP;
     const int m = (int)(item - cell * NP);
     int l[3] = {m % P, (m / P) % P, m / (P * P)};
@@ -288,6 +304,8 @@ dg_status dg_forcing_set_amplitudes(dg_forcing *f, const double *amp)
 dg_status dg_forcing_update(dg_forcing *f, const double *noise, double dt)
 {
     if (!f || !noise || !(dt > 0.0)) return DG_EINVAL;
+    for (int i = 0; i < f->nm * 6; ++i)
+        if (!std::isfinite(noise[i])) return DG_EINVAL;
     const double decay = std::exp(-dt / f->t_corr);   // 0 for dt = +inf: a stationary draw
     const double kick = std::sqrt(1.0 - decay * decay) / std::sqrt(2.0);
     for (int i = 0; i < f->nm; ++i) {
@@ -328,7 +346,8 @@ dg_status dg_forcing_project(dg_forcing *f, double *s, void *stream)
         return DG_EDEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return DG_EDEVICE;
     const long long items = f->ncells * f->NP;
-    const dim3 grid((unsigned)((items + 255) / 256)), block(256);
+    const long long blocks = (items + 255) / 256;
+    const dim3 grid((unsigned)(blocks < (1LL << 20) ? blocks : (1LL << 20))), block(256);
     const void *fn = f->dim == 2 ? (const void *)&forcing_project_kernel<2> : (const void *)&forcing_project_kernel<3>;
     const double *t = f->d_tab;
     int nm = f->nm, kmax = f->kmax, P = f->P, NP = f->NP, basis = f->basis, n0 = f->n[0], n1 = f->n[1];

@@ -43,3 +43,9 @@ def test_forcing_rejects_bad_arguments():
         drv.update(np.zeros((drv.nm, 3, 2)), -1.0)
     with pytest.raises(dg.DgError):
         drv.set_amplitudes(np.full((drv.nm, 3, 2), np.nan))
+    bad = np.zeros((drv.nm, 3, 2))
+    bad[3, 1, 0] = np.inf
+    a0 = drv.amplitudes().copy()
+    with pytest.raises(dg.DgError):
+        drv.update(bad, 0.1)
+    np.testing.assert_array_equal(drv.amplitudes(), a0)       # rejected draws change nothing
