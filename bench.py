@@ -162,6 +162,7 @@ def make_workload(name, order, device, precision):
                 drv.update(noise[state["k"] % len(noise)], every * dt0)
                 state["k"] += 1
                 drv.project(f)
+                s.set_forcing(f)                           # the library re-evaluates it at the Gauss points
         desc = {"workload": "driven_turbulence_3d" + ("_pn" if basis else ""), "cells": [n, n, n], "order": order,
                 "fields": 5, "basis": "P_n (total degree)" if basis else "Q_n (tensor)",
                 "modes": s.nmodes, "physics": "navier_stokes nu=kappa=2e-5 + OU driving", "gamma": 1.0001,

@@ -218,10 +218,14 @@ dg_status dg_max_dt_noalloc(dg_ctx *ctx, const double *w, double *out, void *str
 dg_status dg_conserved_totals(dg_ctx *ctx, const double *w, double *out, void *stream);
 
 /* Body-force acceleration field s (Sec. 7 driving): device array
- * [cell][dim][order^dim] of DG coefficients, read by every later RHS as the
- * momentum source rho s and energy source rho s.v, projected on the basis.
- * The library keeps the pointer (caller keeps the memory alive); NULL
- * removes the forcing. */
+ * [cell][dim][dg_num_modes] of DG coefficients (8-byte aligned), acting in
+ * every later RHS as the momentum source rho s and energy source rho s.v,
+ * projected on the basis.  The library evaluates s at the Gauss points into
+ * its own device buffer (ncells * dim * order^dim values of the bulk type,
+ * allocated by the first call; DG_ENOMEM if that fails).  It does so on the
+ * stream of the next RHS evaluation, reading s_coeffs then: the caller keeps
+ * the array alive and unchanged until that RHS, and calls dg_set_forcing
+ * again after changing the coefficients.  NULL removes the forcing. */
 dg_status dg_set_forcing(dg_ctx *ctx, const double *s_coeffs);
 
 /* ---------------------------------------------------------------------------

@@ -71,7 +71,7 @@ struct VolArgs {
     const double *dt_ptr;   // device dt (used when not null)
     double dt;
     const void *fb;         // face fluxes (T), weighted by the transverse Gauss weights
-    const double *forcing;  // [cell][dim][p^d] or null
+    const void *forcing;    // driving field at the Gauss points [cell][dim][p^d] (T) or null
     const double *R_prev;   // [cell] dlnS/dt of the previous step (AV) or null
     double *R_out;          // [cell] dlnS/dt of `cur` (stage 1) or null
     int *flag;              // error flag: 1 non-physical mean, 2 non-finite

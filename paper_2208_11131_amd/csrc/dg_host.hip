@@ -402,7 +402,10 @@ struct dg_ctx {
     int *flag;
     double *tot_part;
     int tot_blocks, tot_chunk;
-    const double *forcing;
+    const void *forcing;           // driving field at the Gauss points (spts) while forcing is on, else null
+    const double *forcing_src;     // the caller's coefficients, converted before the next RHS
+    void *spts;                    // [cell][dim][p^d] of the bulk type
+    bool forcing_dirty;
     // kernel timing
     int timing;
     std::vector<hipEvent_t> *ev_pool;
@@ -425,6 +428,7 @@ void free_bufs(dg_ctx *c)
     if (c->scal) (void)hipFree(c->scal);
     if (c->flag) (void)hipFree(c->flag);
     if (c->tot_part) (void)hipFree(c->tot_part);
+    if (c->spts) (void)hipFree(c->spts);
 }
 
 void get_kernels(int dim, int prec, int P, int phys, KernelSet *k)
@@ -536,9 +540,28 @@ dg_status launch(dg_ctx *c, int kind, const void *fn, dim3 grid, dim3 block, voi
     return DG_OK;
 }
 
+// Gauss-point values of the caller's driving-field coefficients, after a
+// dg_set_forcing (enqueued on the stream of the next RHS).
+dg_status convert_forcing(dg_ctx *c, hipStream_t s)
+{
+    const int FA = c->NP >= 256 ? 1 : 256 / c->NP;
+    long long narr = c->ncells * c->dim;
+    const double *src = c->forcing_src;
+    void *dst = c->spts;
+    void *args[] = {&src, &dst, &narr};
+    const dim3 g((unsigned)((narr + FA - 1) / FA));
+    if (!ok(hipLaunchKernel(c->ks.fpts, g, dim3(256), args, 0, s))) return DG_EDEVICE;
+    c->forcing_dirty = false;
+    return DG_OK;
+}
+
 // One RHS evaluation of `in` followed by the stage combination of VolArgs.
 dg_status stage(dg_ctx *c, dgk::VolArgs va, hipStream_t s)
 {
+    if (c->forcing && c->forcing_dirty) {
+        const dg_status fs = convert_forcing(c, s);
+        if (fs != DG_OK) return fs;
+    }
     dgk::FaceArgs fa;
     fa.w = va.cur;
     fa.fb = c->fb;
@@ -859,7 +882,6 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
 
     // launch tiles: explicit options, else the tuned table, else about 256
     // volume points / 128 face points per block
-    const int Fx = c->F + d;
     const TileEntry *te = find_tiles(d, order, c->precision, c->phys, 0);
     if (o.cells_per_block > 0)
         c->vol_C = o.cells_per_block;
@@ -867,7 +889,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         c->vol_C = te->vol_C;
     else
         c->vol_C = std::max(1, 256 / c->NP);
-    while (c->vol_C > 1 && c->ks.vol_lds(c->vol_C, Fx) > LDS_MAX) --c->vol_C;
+    while (c->vol_C > 1 && c->ks.vol_lds(c->vol_C, c->F) > LDS_MAX) --c->vol_C;
     if (o.vol_threads > 0)
         c->vol_T = o.vol_threads;
     else if (te && o.cells_per_block == 0)
@@ -875,7 +897,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     else
         c->vol_T = std::min(512, std::max(64, roundup(c->vol_C * c->NP, 64)));
     c->vol_lds = c->ks.vol_lds(c->vol_C, c->F);
-    c->vol_lds_forced = c->ks.vol_lds(c->vol_C, Fx);
+    c->vol_lds_forced = c->ks.vol_lds(c->vol_C, c->F);   // the driving field takes no LDS
     if (c->vol_lds > LDS_MAX) {
         delete c;
         return DG_EUNSUPPORTED;
@@ -1172,9 +1194,25 @@ dg_status dg_conserved_totals(dg_ctx *c, const double *w, double *out, void *str
 
 dg_status dg_set_forcing(dg_ctx *c, const double *s_coeffs)
 {
-    if (!c) return DG_EINVAL;
-    if (s_coeffs && c->vol_lds_forced > LDS_MAX) return DG_EUNSUPPORTED;
-    c->forcing = s_coeffs;
+    if (!c || ((uintptr_t)s_coeffs & 7)) return DG_EINVAL;
+    if (!s_coeffs) {
+        c->forcing = nullptr;
+        c->forcing_src = nullptr;
+        c->forcing_dirty = false;
+        return DG_OK;
+    }
+    if (c->vol_lds_forced > LDS_MAX || !c->ks.fpts) return DG_EUNSUPPORTED;
+    if (!c->spts) {
+        const size_t tsz = c->precision == DG_PREC_FP64 ? sizeof(double) : sizeof(float);
+        if (!ok(hipMalloc(&c->spts, (size_t)c->ncells * c->dim * c->NP * tsz))) {
+            (void)hipGetLastError();
+            c->spts = nullptr;
+            return DG_ENOMEM;
+        }
+    }
+    c->forcing_src = s_coeffs;
+    c->forcing = c->spts;
+    c->forcing_dirty = true;
     return DG_OK;
 }
 

@@ -22,6 +22,7 @@ void fill(KernelSet *k)
     k->cfl_lds = &cfl_lds_bytes<2, P>;
     k->limit = (const void *)&limit_kernel<2, P, PH>;
     k->limit_lds = &lim_lds_bytes<2, P>;
+    k->fpts = (const void *)&forcing_points_kernel<2, P, double, Fld<2, PH>::PN>;
 }
 
 template <int P>

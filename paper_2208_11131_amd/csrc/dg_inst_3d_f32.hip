@@ -22,6 +22,7 @@ void fill(KernelSet *k)
     k->cfl_lds = nullptr;
     k->limit = nullptr;
     k->limit_lds = nullptr;
+    k->fpts = (const void *)&forcing_points_kernel<3, P, float, Fld<3, PH>::PN>;
 }
 
 template <int P>

@@ -941,7 +941,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     constexpr int NM = BS::NM;                // stored modes per field
     constexpr int FNP = F * NM;               // stored weights per cell
     const bool forced = FO >= 0 ? FO == 1 : a.forcing != nullptr;
-    const int Fx = F + (forced ? D : 0);
+    constexpr int Fx = F;                     // arrays of the modal -> point passes
     const int C = CC > 0 ? CC : a.cells_per_block;
     constexpr int NAP = Pad<P>::PP * NP / P;  // padded per-cell array
     const int CNP = C * NAP;                  // one field of the tile
@@ -952,8 +952,9 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     // LDS, field-major: Ub [field][cell][point] (point values, then sources),
     // G [axis][field][cell][point] (gradients, then fluxes); points in the
     // padded layout of Pad<P>.  The ping-pong buffer of the contraction
-    // passes lives in G's space (D F >= F + D arrays), which is free outside
-    // the gradient / flux phases.
+    // passes lives in G's space (D F >= F arrays), which is free outside
+    // the gradient / flux phases.  The driving field is read at the Gauss
+    // points from HBM by the source step (no LDS).
     long long *fidx = (long long *)smem;      // [C][D][2] lower/upper face index per axis
     double *cellv = (double *)(fidx + 2 * D * C);   // [C]: wiggle source
     double *cmean = cellv + C;                // [C][D+2]: new cell means (checks)
@@ -1011,8 +1012,8 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
 
     // 2. point values of all fields: one operator pass per axis.  The pass
     //    along x reads each line's p modal weights (contiguous in HBM)
-    //    straight from the state or forcing arrays, so the weights never
-    //    pass through LDS; the same FMA chain as the LDS passes.
+    //    straight from the state, so the weights never pass through LDS;
+    //    the same FMA chain as the LDS passes.
     // With a fixed tile, line q = tid + r NT of this pass (r < KEEP) is also
     // line r of the final projection / RK pass of this thread: its FP64
     // weights are kept in registers for the RK combination (no second read).
@@ -1034,11 +1035,10 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
                 // the line's l_x modes (zeros above total degree n)
                 const int ly = t % P, lz = t / P;
                 const int o0 = BS::off(ly, lz), nl = BS::len(ly, lz);
-                const double *src = f < F ? a.cur + cc * FNP + f * NM + o0
-                                          : a.forcing + cc * (D * NM) + (f - F) * NM + o0;
+                const double *src = a.cur + cc * FNP + f * NM + o0;
 #pragma unroll
                 for (int k = 0; k < P; ++k) x[k] = (T)(k < nl ? src[k] : 0.0);
-            } else if (f < F) {
+            } else {
                 const double *src = a.cur + cc * FNP + f * NP + t * P;
 #pragma unroll
                 for (int k = 0; k < P; k += VWL) {
@@ -1049,10 +1049,6 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
                         if (keep) keep[k + h] = v.x[h];
                     }
                 }
-            } else {
-                const double *src = a.forcing + cc * (D * NP) + (f - F) * NP + t * P;
-#pragma unroll
-                for (int k = 0; k < P; ++k) x[k] = (T)src[k];
             }
             const int o = pad_line_offset<P, D, 0>(q);
 #pragma unroll
@@ -1092,12 +1088,16 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         const int cq = qq / NP, j = qq - cq * NP;
         const int q = cq * NAP + ppos<P>(j);   // padded position of point j of cell cq
         T u[F + D];
+        if (forced) {
+            // driving field at this Gauss point (tail cells: the last cell's)
+            long long cc = c0 + cq;
+            if (cc >= NC) cc = NC - 1;
+            const T *sp = (const T *)a.forcing + cc * (D * NP) + j;
+#pragma unroll
+            for (int i = 0; i < D; ++i) u[F + i] = sp[i * NP];
+        }
 #pragma unroll
         for (int f = 0; f < F; ++f) u[f] = U[f * CNP + q];
-        if (forced) {
-#pragma unroll
-            for (int i = 0; i < D; ++i) u[F + i] = U[(F + i) * CNP + q];
-        }
         int jr = j;
         T wq = T(1);
 #pragma unroll
@@ -1526,6 +1526,72 @@ template <int D, int P, typename T, int PH, int C, int NT>
 __global__ void __launch_bounds__(NT) vol_kernel_batched_fixed(const BoxDesc *boxes, int nbox, StageDesc sd)
 {
     vol_batched_body<D, P, T, PH, C, NT>(boxes, nbox, sd);
+}
+
+// Gauss-point values of the driving-field coefficients (Sec. 7.1): arrays
+// [cell][dim][modes] (FP64, in the layout of the basis) become point values
+// [cell][dim][p^d] (j = j_x + p (j_y + p j_z)) in the bulk type T, by the line
+// passes of the volume kernel's modal -> point transform (x, then y, then z;
+// the same operator entries and FMA order, so the same bits).  The volume
+// kernel reads them at its source step.  A block takes FA arrays.
+template <int D, int P, typename T, bool PN>
+__global__ void __launch_bounds__(256) forcing_points_kernel(const double *__restrict__ s, T *__restrict__ out,
+                                                             long long narr)
+{
+    constexpr int NP = ipow(P, D);
+    constexpr int K = NP / P;
+    using BS = Basis<D, P, PN>;
+    constexpr int NM = BS::NM;
+    constexpr int FA = NP >= 256 ? 1 : 256 / NP;
+    __shared__ T X[FA * NP], Y[FA * NP];
+    const long long g0 = (long long)blockIdx.x * FA;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int q = tid; q < FA * K; q += nt) {          // pass along x from the coefficients
+        const int ar = q / K, t = q - ar * K;
+        const long long g = g0 + ar;
+        if (g >= narr) continue;
+        const int ly = t % P, lz = t / P;
+        const double *src = s + g * NM + (PN ? BS::off(ly, lz) : t * P);
+        const int nl = PN ? BS::len(ly, lz) : P;
+        T x[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = (T)(k < nl ? src[k] : 0.0);
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_B>(k, i), x[k], acc);
+            X[ar * NP + t * P + i] = acc;
+        }
+    }
+    __syncthreads();
+    T *in = X, *o = Y;
+#pragma unroll
+    for (int ax = 1; ax < D; ++ax) {                  // passes along y (and z)
+        const int S = ax == 1 ? P : P * P;
+        for (int q = tid; q < FA * K; q += nt) {
+            const int ar = q / K, t = q - ar * K;
+            const int base = ar * NP + (ax == 1 ? (t % P) + P * P * (t / P) : t);
+            T x[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) x[k] = in[base + k * S];
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                T acc = T(0);
+#pragma unroll
+                for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_B>(k, i), x[k], acc);
+                o[base + i * S] = acc;
+            }
+        }
+        __syncthreads();
+        T *tmp = in;
+        in = o;
+        o = tmp;
+    }
+    for (int q = tid; q < FA * NP; q += nt) {
+        const long long g = g0 + q / NP;
+        if (g < narr) out[g * NP + q % NP] = in[q];
+    }
 }
 
 template <int D, int P, typename T, int PH>

@@ -7,8 +7,10 @@
 namespace dgk {
 
 // Kernels and LDS-size functions of one (dim, order, precision, physics)
-// instantiation; physics PH = 0 Euler, 1 Navier-Stokes, 2 artificial viscosity.  The function pointers are the host stubs of __global__
-// functions, launched with hipLaunchKernel.
+// instantiation; physics PH = 0 Euler, 1 Navier-Stokes, 2 artificial
+// viscosity, 3 Navier-Stokes with the tracer, 4 / 5 Euler / Navier-Stokes on
+// the total-degree basis.  The function pointers are the host stubs of
+// __global__ functions, launched with hipLaunchKernel.
 struct KernelSet {
     const void *vol;
     const void *face;
@@ -21,6 +23,7 @@ struct KernelSet {
     size_t (*cfl_lds)(int C, int nt);
     const void *limit;     // positivity limiter (FP64 units only)
     size_t (*limit_lds)(int C, int nt);
+    const void *fpts;      // driving field -> Gauss-point values (256 threads, grid: arrays / FA)
 };
 
 void dgk_get_2d_f64(int P, int ph, KernelSet *k);
