@@ -122,18 +122,16 @@ struct StageDesc {
     double c_base, c_cur, c_L, d_x2, d_cur, d_L;
 };
 
-// Number of face blocks (grid.x) for pencils of C faces: the largest over the
-// directions of ceil(nf[a] / C) times the extents of the other axes.
-inline long long face_pencils(const Geo &g, int dim, int C)
+// Launch grid of the single-box face kernels: bricks of C cells per axis,
+// ceil(nf[a] / C) along axis a, each with dim C^(dim-1) pencil blocks (all
+// directions); grid.x = those blocks times the bricks along x, grid.y and
+// grid.z the bricks along y and z.
+inline void face_grid(const Geo &g, int dim, int C, long long &gx, long long &gy, long long &gz)
 {
-    long long mx = 0;
-    for (int a = 0; a < dim; ++a) {
-        long long n = (g.nf[a] + C - 1) / C;
-        for (int b = 0; b < 3; ++b)
-            if (b != a) n *= g.n[b];
-        if (n > mx) mx = n;
-    }
-    return mx;
+    const long long k1 = dim == 3 ? (long long)C * C : C;
+    gx = dim * k1 * ((g.nf[0] + C - 1) / C);
+    gy = (g.nf[1] + C - 1) / C;
+    gz = dim == 3 ? (g.nf[2] + C - 1) / C : 1;
 }
 
 }  // namespace dgk

@@ -580,7 +580,9 @@ dg_status stage(dg_ctx *c, dgk::VolArgs va, hipStream_t s)
         c->fin_pending = false;
     }
     void *fargs[] = {&c->ph, &c->geo, &fa};
-    dim3 fg((unsigned)dgk::face_pencils(c->geo, c->dim, c->face_C), (unsigned)c->dim);
+    long long fgx, fgy, fgz;
+    dgk::face_grid(c->geo, c->dim, c->face_C, fgx, fgy, fgz);
+    dim3 fg((unsigned)fgx, (unsigned)fgy, (unsigned)fgz);
     dg_status st = launch(c, 0, c->face_fixed ? c->face_fixed : c->ks.face, fg, dim3(c->face_T), fargs,
                           c->face_lds, s);
     if (st != DG_OK) return st;
@@ -916,6 +918,15 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     else
         c->face_T = std::min(512, std::max(64, roundup(c->face_C * c->K, 64)));
     c->face_lds = std::max<size_t>(c->ks.face_lds(c->face_C), 256);   // >= the CFL finalize's 16 doubles
+    {
+        // the face launch (face_grid) within the grid limits and 32-bit block indices
+        long long gx, gy, gz;
+        dgk::face_grid(c->geo, d, c->face_C, gx, gy, gz);
+        if (gx * c->face_T > 0xFFFFFFFFLL || gy > 65535 || gz > 65535 || gx * gy * gz > 0xFFFFFFFFLL) {
+            delete c;
+            return DG_EUNSUPPORTED;
+        }
+    }
     c->cfl_C = std::max(1, 256 / c->NP);
     c->cfl_T = 256;
     while (c->cfl_C > 1 && c->ks64.cfl_lds(c->cfl_C, c->cfl_T) > 64 * 1024) --c->cfl_C;

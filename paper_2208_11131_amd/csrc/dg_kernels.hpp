@@ -440,10 +440,11 @@ __device__ __forceinline__ T clamp_alpha(T al, T amax)
 // separate once, so every cell is read about once per direction.
 
 // CC, NTC: faces per pencil and threads per block fixed at compile time (0 =
-// taken from the launch); same results either way.
+// taken from the launch); same results either way.  The pencil: faces
+// a0 .. a0 + C - 1 along AX at the transverse cell coordinates cin[b != AX].
 template <int D, int P, int AX, typename T, int PH, int CC = 0, int NTC = 0>
 __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const FaceArgs &a, unsigned char *smem,
-                                          long long pen_id)
+                                          const int *cin, int a0)
 {
     constexpr int NP = ipow(P, D);
     constexpr int K = NP / P;          // face points (and transverse modes)
@@ -464,23 +465,9 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     const int tid = threadIdx.x, nt = NTC > 0 ? NTC : (int)blockDim.x;
     const int Q = C * F * NAF;
     const int na = geo.n[AX], nfa = geo.nf[AX];
-    // pencil coordinates in 32 bits (the host bounds the counts by 2^31)
-    const unsigned npl = (unsigned)((nfa + C - 1) / C);
-    const unsigned line = (unsigned)pen_id / npl;
-    const int a0 = (int)((unsigned)pen_id - line * npl) * C;
     const int nface = min(C, nfa - a0);
-    int co[3] = {0, 0, 0};
-    {
-        unsigned r = line;
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-            if (b != AX) {
-                const unsigned nb = (unsigned)geo.n[b];
-                const unsigned q = r / nb;
-                co[b] = (int)(r - q * nb);
-                r = q;
-            }
-    }
+    int co[3] = {cin[0], cin[1], cin[2]};
+    co[AX] = 0;
 
     long long *cellidx = (long long *)smem;               // [C+1]
     int *mir = (int *)(cellidx + (C + 1));                // [C+1]
@@ -723,16 +710,68 @@ __device__ __forceinline__ long long pencils(const Geo &geo, int ax, int C)
     return npen;
 }
 
+// Pencil pen of direction ax in line order (lines of the transverse cell
+// coordinates, first transverse axis fastest; pencils along a line fastest),
+// the enumeration of the grouped launches.  32-bit arithmetic (the host
+// bounds the counts by 2^31).
+__device__ __forceinline__ void pencil_coords(const Geo &geo, int C, int ax, long long pen, int *co, int &a0)
+{
+    const unsigned npl = (unsigned)((geo.nf[ax] + C - 1) / C);
+    const unsigned line = (unsigned)pen / npl;
+    a0 = (int)((unsigned)pen - line * npl) * C;
+    co[0] = co[1] = co[2] = 0;
+    unsigned r = line;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        if (b != ax) {
+            const unsigned nb = (unsigned)geo.n[b];
+            const unsigned q = r / nb;
+            co[b] = (int)(r - q * nb);
+            r = q;
+        }
+}
+
+// Block -> pencil map of the single-box face launch (grid of face_grid):
+// bricks of C cells per axis, x fastest; each brick's pencils of all
+// directions (C^(D-1) per direction, the directions alternating) are
+// consecutive blocks, so the three reads of a cell (one per direction) fall
+// close together in time on one XCD and the second and third come from L2.
+// Returns false for the blocks of a brick beyond the mesh.
+__device__ __forceinline__ bool face_brick(const Geo &geo, int D, int C, int &ax, int *co, int &a0)
+{
+    const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+    const unsigned L = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+    const unsigned K1 = (D == 3) ? (unsigned)(C * C) : (unsigned)C;   // pencils per direction and brick
+    const unsigned S = (unsigned)D * K1;
+    const unsigned brick = L / S, s = L - brick * S;
+    ax = (int)(s % (unsigned)D);
+    const unsigned j = s / (unsigned)D;
+    const unsigned B0 = (unsigned)((geo.nf[0] + C - 1) / C), B1 = (unsigned)((geo.nf[1] + C - 1) / C);
+    const unsigned r = brick / B0;
+    const unsigned b[3] = {brick - r * B0, r % B1, r / B1};
+    const int t1 = (ax == 0) ? 1 : 0, t2 = (ax == 2) ? 1 : 2;   // transverse axes
+    a0 = (int)(b[ax] * (unsigned)C);
+    if (a0 >= geo.nf[ax]) return false;
+    co[0] = co[1] = co[2] = 0;
+    co[t1] = (int)(b[t1] * (unsigned)C + j % (unsigned)C);
+    if (co[t1] >= geo.n[t1]) return false;
+    if (D == 3) {
+        co[t2] = (int)(b[t2] * (unsigned)C + j / (unsigned)C);
+        if (co[t2] >= geo.n[t2]) return false;
+    }
+    return true;
+}
+
 template <int D, int P, typename T, int PH, int CC = 0, int NTC = 0>
 __device__ __forceinline__ void face_dispatch(const Phys &ph, const Geo &geo, const FaceArgs &a, unsigned char *smem,
-                                              int ax, long long pen)
+                                              int ax, const int *co, int a0)
 {
     if (ax == 0)
-        face_body<D, P, 0, T, PH, CC, NTC>(ph, geo, a, smem, pen);
+        face_body<D, P, 0, T, PH, CC, NTC>(ph, geo, a, smem, co, a0);
     else if (ax == 1)
-        face_body<D, P, 1, T, PH, CC, NTC>(ph, geo, a, smem, pen);
+        face_body<D, P, 1, T, PH, CC, NTC>(ph, geo, a, smem, co, a0);
     else if (D == 3)
-        face_body<D, P, (D == 3 ? 2 : 0), T, PH, CC, NTC>(ph, geo, a, smem, pen);
+        face_body<D, P, (D == 3 ? 2 : 0), T, PH, CC, NTC>(ph, geo, a, smem, co, a0);
 }
 
 // The CFL finalize carried by a face launch: block (0, 0) reduces the CFL
@@ -741,7 +780,7 @@ __device__ __forceinline__ void face_dispatch(const Phys &ph, const Geo &geo, co
 // The next kernel on the stream (the volume kernel of the same stage) reads it.
 __device__ __forceinline__ void face_cfl_finalize(const FaceArgs &a, unsigned char *smem)
 {
-    if (!a.cfl_part || blockIdx.x != 0 || blockIdx.y != 0) return;
+    if (!a.cfl_part || blockIdx.x != 0 || blockIdx.y != 0 || blockIdx.z != 0) return;
     const int nt = blockDim.x;
     const double2 *pp = (const double2 *)a.cfl_part;
     double c = 0.0, v = 0.0;
@@ -781,10 +820,9 @@ __global__ void __launch_bounds__(512) face_kernel(Phys ph, Geo geo, FaceArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     face_cfl_finalize(a, smem);
-    const int ax = blockIdx.y;
-    const unsigned bid = xcd_block(blockIdx.x, gridDim.x);
-    if ((long long)bid >= pencils(geo, ax, a.faces_per_block)) return;
-    face_dispatch<D, P, T, PH>(ph, geo, a, smem, ax, bid);
+    int ax, co[3], a0;
+    if (!face_brick(geo, D, a.faces_per_block, ax, co, a0)) return;
+    face_dispatch<D, P, T, PH>(ph, geo, a, smem, ax, co, a0);
 }
 
 // Face kernel with the pencil length C and block size NT fixed at compile
@@ -796,10 +834,9 @@ __global__ void __launch_bounds__(NT) face_kernel_fixed(Phys ph, Geo geo, FaceAr
     extern __shared__ __align__(16) unsigned char smem[];
     if (a.faces_per_block != C) return;   // host selection error
     face_cfl_finalize(a, smem);
-    const int ax = blockIdx.y;
-    const unsigned bid = xcd_block(blockIdx.x, gridDim.x);
-    if ((long long)bid >= pencils(geo, ax, C)) return;
-    face_dispatch<D, P, T, PH, C, NT>(ph, geo, a, smem, ax, bid);
+    int ax, co[3], a0;
+    if (!face_brick(geo, D, C, ax, co, a0)) return;
+    face_dispatch<D, P, T, PH, C, NT>(ph, geo, a, smem, ax, co, a0);
 }
 
 // Index of the box owning flat block b of a grouped launch.
@@ -838,7 +875,9 @@ __device__ __forceinline__ void face_batched_body(const BoxDesc *boxes, int nbox
     for (int ax = 0; ax < D; ++ax) {
         const long long n = pencils(geo, ax, a.faces_per_block);
         if (loc < n) {
-            face_dispatch<D, P, T, PH, CC, NTC>(ph, geo, a, smem, ax, loc);
+            int co[3], a0;
+            pencil_coords(geo, a.faces_per_block, ax, loc, co, a0);
+            face_dispatch<D, P, T, PH, CC, NTC>(ph, geo, a, smem, ax, co, a0);
             return;
         }
         loc -= n;
