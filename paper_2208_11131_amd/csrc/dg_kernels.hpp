@@ -477,6 +477,17 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
     // are read straight from HBM by the normal contraction.
     T *Sx = (T *)(smem + (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16);   // [5][C][F][NAF]
     T *A = Sx + 5 * Q;                                    // [NA][C][F][NAF]
+    // P_n with gradients: the recovery vectors of every transverse degree,
+    // [vL, dL, vR, dR][tau][m], copied to LDS (each lane of the contraction
+    // indexes them by its own line's degree)
+    T *rt = A + NA * Q;
+    if constexpr (PN && GRAD) {
+        const Tab<T> &tb = TabSel<T>::get(P);
+        for (int i = tid; i < 4 * P * P; i += nt) {
+            const int w = i / (P * P), r = i - w * (P * P), tau = r / P, m = r - tau * P;
+            rt[i] = w == 0 ? tb.prvL[tau][m] : (w == 1 ? tb.prdL[tau][m] : (w == 2 ? tb.prvR[tau][m] : tb.prdR[tau][m]));
+        }
+    }
 
     // ghost slots of non-periodic ends: mir = 1 mirrored ghost (odd normal
     // modes negated), 2 reflecting wall (the same, and the normal momentum
@@ -527,12 +538,22 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                 const int t0 = lo + hi * S * P;            // tensor index of normal digit 0
                 tau = t0 % P + (t0 / P) % P + t0 / (P * P);
                 const double *cp = a.w + cellidx[sl] * FNP + f * NM;
+                if constexpr (AX == 0) {
+                    // the x-line of transverse degrees (l_y, l_z) is stored contiguously
+                    const double *lp = cp + BS::off(t0 / P % P, t0 / (P * P));
 #pragma unroll
-                for (int m = 0; m < P; ++m) {
-                    const int ti = t0 + m * S;
-                    const int id = BS::idx(ti % P, (ti / P) % P, ti / (P * P));
-                    const double v = id >= 0 ? cp[id] : 0.0;
-                    x[m] = (T)(((mr && (m & 1)) != wn) ? -v : v);
+                    for (int m = 0; m < P; ++m) {
+                        const double v = m < P - tau ? lp[m] : 0.0;
+                        x[m] = (T)(((mr && (m & 1)) != wn) ? -v : v);
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const int ti = t0 + m * S;
+                        const int id = BS::idx(ti % P, (ti / P) % P, ti / (P * P));
+                        const double v = id >= 0 ? cp[id] : 0.0;
+                        x[m] = (T)(((mr && (m & 1)) != wn) ? -v : v);
+                    }
                 }
             } else if (AX == 0 && P % 2 == 0) {
 #pragma unroll
@@ -548,6 +569,9 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                     x[m] = (T)(((mr && (m & 1)) != wn) ? -v : v);
                 }
             }
+            // table row of the recovery vectors (lines beyond the basis, tau > n,
+            // hold zeros: any row gives their exact 0; the LDS table has p rows)
+            const int trow = tau < P ? tau : P - 1;
             const int pt = ppos<P, PP>(t);
             if (sl < C) {
                 const int qa = (sl * F + f) * NAF + pt;
@@ -556,7 +580,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                 for (int m = 0; m < P; ++m) tl = fma(tb.ep[m], x[m], tl);
                 A[0 * Q + qa] = tl;
                 if (GRAD) {
-                    const T *vL = PN ? tb.prvL[tau] : tb.rvL, *dL = PN ? tb.prdL[tau] : tb.rdL;
+                    const T *vL = PN ? rt + trow * P : tb.rvL, *dL = PN ? rt + (P + trow) * P : tb.rdL;
                     T rv = T(0), rn = T(0);
 #pragma unroll
                     for (int m = 0; m < P; ++m) {
@@ -574,7 +598,7 @@ __device__ __forceinline__ void face_body(const Phys &ph, const Geo &geo, const 
                 for (int m = 0; m < P; ++m) tr = fma(tb.em[m], x[m], tr);
                 A[1 * Q + qa] = tr;
                 if (GRAD) {
-                    const T *vR = PN ? tb.prvR[tau] : tb.rvR, *dR = PN ? tb.prdR[tau] : tb.rdR;
+                    const T *vR = PN ? rt + (2 * P + trow) * P : tb.rvR, *dR = PN ? rt + (3 * P + trow) * P : tb.rdR;
                     T rv = T(0), rn = T(0);
 #pragma unroll
                     for (int m = 0; m < P; ++m) {
@@ -910,7 +934,8 @@ size_t face_lds_bytes(int C)
     const size_t hdr = (((C + 1) * (sizeof(long long) + sizeof(int)) + 15) / 16) * 16;
     const size_t Q = (size_t)C * F * (PP * K / P);
     const size_t NA = Fld<D, PH>::GRAD ? 4 : 2;
-    const size_t tot = 5 * Q + NA * Q;
+    const size_t rt = (Fld<D, PH>::PN && Fld<D, PH>::GRAD) ? 4 * P * P : 0;   // P_n recovery vectors
+    const size_t tot = 5 * Q + NA * Q + rt;
     return hdr + sizeof(T) * tot;
 }
 
