@@ -80,3 +80,34 @@ def test_driven_turbulence_steps_with_ou_updates():
     e = state_err(w.cpu().numpy(), wr, 3, mom_scale=momentum_scale(ref, wr))
     say("  state err after 9 driven steps %.2e" % e)
     assert e <= 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_set_forcing_reevaluates_each_call(precision, tol):
+    """dg_set_forcing evaluates the coefficients at the Gauss points for the
+    next RHS: a new field (same device array, new values) after a second
+    call, no field after NULL, each matching the oracle (FP64 bar, and the
+    FP32-bulk bar of the rounding scale)."""
+    from oracle.compare import rhs_err
+    order, n = 4, (5, 4, 3)
+    h = 1.0 / n[0]
+    say("set_forcing re-evaluation", precision)
+    gpu = dg.Solver(3, n, order, 1.0001, nu=2e-5, kappa=2e-5, hi=[n[a] * h for a in range(3)], precision=precision)
+    ref = O.Problem(3, n, h, order, 1.0001, nu=2e-5, kappa=2e-5)
+    w0 = W.random_smooth(3, n, order, seed=11, amp=0.08, vbase=(0.2, -0.1, 0.1)).numpy()
+    w = torch.tensor(w0, device="cuda")
+    rng = np.random.default_rng(12)
+    s_dev = torch.empty(gpu.ncells * 3 * gpu.nmodes, dtype=torch.float64, device="cuda")
+    for k in range(2):
+        s = rng.normal(0.0, 0.3, (gpu.ncells, 3, gpu.nmodes))
+        s_dev.copy_(torch.tensor(s.reshape(-1)))
+        gpu.set_forcing(s_dev)
+        ref.set_forcing(s)
+        e = rhs_err(gpu.rhs(w).cpu().numpy(), ref.rhs(w0), ref.rhs_abs(w0), 3)
+        say("  field %d: rhs err / rounding scale %.2e" % (k, e))
+        assert e <= tol
+    gpu.set_forcing(None)
+    ref.set_forcing(None)
+    e = rhs_err(gpu.rhs(w).cpu().numpy(), ref.rhs(w0), ref.rhs_abs(w0), 3)
+    say("  no field: rhs err / rounding scale %.2e" % e)
+    assert e <= tol
