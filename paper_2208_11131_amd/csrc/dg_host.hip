@@ -549,7 +549,8 @@ dg_status convert_forcing(dg_ctx *c, hipStream_t s)
     const double *src = c->forcing_src;
     void *dst = c->spts;
     void *args[] = {&src, &dst, &narr};
-    const dim3 g((unsigned)((narr + FA - 1) / FA));
+    const long long groups = (narr + FA - 1) / FA;
+    const dim3 g((unsigned)std::min<long long>(groups, 1LL << 20));   // grid-stride kernel
     if (!ok(hipLaunchKernel(c->ks.fpts, g, dim3(256), args, 0, s))) return DG_EDEVICE;
     c->forcing_dirty = false;
     return DG_OK;
@@ -898,6 +899,11 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
         c->vol_T = te->vol_T;
     else
         c->vol_T = std::min(512, std::max(64, roundup(c->vol_C * c->NP, 64)));
+    // one volume block per vol_C cells: the launch must stay below 2^32 work-items
+    if ((c->ncells + c->vol_C - 1) / c->vol_C * (long long)c->vol_T > 0xFFFFFFFFLL) {
+        delete c;
+        return DG_EUNSUPPORTED;
+    }
     c->vol_lds = c->ks.vol_lds(c->vol_C, c->F);
     c->vol_lds_forced = c->ks.vol_lds(c->vol_C, c->F);   // the driving field takes no LDS
     if (c->vol_lds > LDS_MAX) {

@@ -1608,8 +1608,9 @@ __global__ void __launch_bounds__(256) forcing_points_kernel(const double *__res
     constexpr int NM = BS::NM;
     constexpr int FA = NP >= 256 ? 1 : 256 / NP;
     __shared__ T X[FA * NP], Y[FA * NP];
-    const long long g0 = (long long)blockIdx.x * FA;
     const int tid = threadIdx.x, nt = blockDim.x;
+    // grid-stride over groups of FA arrays (the grid is capped by the host)
+    for (long long g0 = (long long)blockIdx.x * FA; g0 < narr; g0 += (long long)gridDim.x * FA) {
     for (int q = tid; q < FA * K; q += nt) {          // pass along x from the coefficients
         const int ar = q / K, t = q - ar * K;
         const long long g = g0 + ar;
@@ -1655,6 +1656,8 @@ __global__ void __launch_bounds__(256) forcing_points_kernel(const double *__res
     for (int q = tid; q < FA * NP; q += nt) {
         const long long g = g0 + q / NP;
         if (g < narr) out[g * NP + q % NP] = in[q];
+    }
+    __syncthreads();   // X / Y are reused by the next group
     }
 }
 
