@@ -6,7 +6,7 @@
 namespace dgk {
 
 constexpr int MAXP = 8;     // highest order (modes / Gauss points per axis)
-constexpr int MAXF = 9;     // stored fields (dim+2, +1 tracer or AV) plus dim forcing fields
+constexpr int MAXF = 9;     // a point's values: stored fields (dim+2, +1 tracer or AV) plus dim forcing components
 
 // Per-order 1D tables on the p Gauss-Legendre nodes x_j of [-1, 1]
 // (Sec. 2.3 scaled Legendre basis, Sec. 2.4 quadrature, Sec. 3.2 recovery).

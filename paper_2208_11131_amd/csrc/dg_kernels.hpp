@@ -7,7 +7,8 @@
 // Work decomposition (one HIP thread block = a tile of whole cells or a pencil
 // of faces; intermediates in LDS, the state read from and written to HBM by
 // the passes that need it):
-//   face kernel    a pencil of faces of direction a = blockIdx.y: traces of
+//   face kernel    a pencil of faces of one direction (blocks in brick-major
+//                  order, all directions of a brick together): traces of
 //                  both cells (normal lines read from HBM), HLLC, and
 //                  (viscous/AV) the interface recovery of Sec. 3.2 with the
 //                  Navier-Stokes/AV flux; one single-valued flux per face
@@ -1005,7 +1006,6 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     constexpr int NM = BS::NM;                // stored modes per field
     constexpr int FNP = F * NM;               // stored weights per cell
     const bool forced = FO >= 0 ? FO == 1 : a.forcing != nullptr;
-    constexpr int Fx = F;                     // arrays of the modal -> point passes
     const int C = CC > 0 ? CC : a.cells_per_block;
     constexpr int NAP = Pad<P>::PP * NP / P;  // padded per-cell array
     const int CNP = C * NAP;                  // one field of the tile
@@ -1025,7 +1025,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     int *blkflag = (int *)(cmean + C * (D + 2));
     double *m0s = (double *)(smem + vol_hdr_bytes<D>(C));   // [Fc][C][K] FP64 surface sums
     T *Ub = (T *)(smem + vol_hdr_bytes<D>(C) + vol_m0_bytes<D, P>(C, Fc));
-    T *G = Ub + Fx * CNP;
+    T *G = Ub + F * CNP;
     T *X0 = (D == 3) ? G : Ub;     // the last of the D passes lands in Ub
     T *X1 = (D == 3) ? Ub : G;
     const Tab<T> &tb = TabSel<T>::get(P);
@@ -1088,7 +1088,7 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
     double pcu[KEEP > 0 ? KEEP : 1][P];
     {
         constexpr int VWL = (P % 2 == 0) ? 2 : 1;       // state weights per load
-        const int nitems = Fx * C * K;                  // K = p^(d-1) lines per array
+        const int nitems = F * C * K;                   // K = p^(d-1) lines per array
         auto first_line = [&](int q, double *keep) {
             const int arr = q / K, t = q - arr * K;
             const int f = arr / C, c = arr - f * C;
@@ -1129,10 +1129,10 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         for (int q = tid + KEEP * nt; q < nitems; q += nt) first_line(q, nullptr);
     }
     __syncthreads();
-    line_pass_pad<P, D, 1, T, M_B, false, NTC>(X1, X0, Fx * C);
+    line_pass_pad<P, D, 1, T, M_B, false, NTC>(X1, X0, F * C);
     __syncthreads();
     if (D == 3) {
-        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_B, false, NTC>(X0, X1, Fx * C);
+        line_pass_pad<P, D, (D == 3 ? 2 : 0), T, M_B, false, NTC>(X0, X1, F * C);
         __syncthreads();
     }
     T *U = (D == 3) ? X1 : X0;
@@ -1611,63 +1611,63 @@ __global__ void __launch_bounds__(256) forcing_points_kernel(const double *__res
     const int tid = threadIdx.x, nt = blockDim.x;
     // grid-stride over groups of FA arrays (the grid is capped by the host)
     for (long long g0 = (long long)blockIdx.x * FA; g0 < narr; g0 += (long long)gridDim.x * FA) {
-    for (int q = tid; q < FA * K; q += nt) {          // pass along x from the coefficients
-        const int ar = q / K, t = q - ar * K;
-        const long long g = g0 + ar;
-        if (g >= narr) continue;
-        const int ly = t % P, lz = t / P;
-        const double *src = s + g * NM + (PN ? BS::off(ly, lz) : t * P);
-        const int nl = PN ? BS::len(ly, lz) : P;
-        T x[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = (T)(k < nl ? src[k] : 0.0);
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            T acc = T(0);
-#pragma unroll
-            for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_B>(k, i), x[k], acc);
-            X[ar * NP + t * P + i] = acc;
-        }
-    }
-    __syncthreads();
-    T *in = X, *o = Y;
-#pragma unroll
-    for (int ax = 1; ax < D; ++ax) {                  // passes along y (and z)
-        const int S = ax == 1 ? P : P * P;
-        for (int q = tid; q < FA * K; q += nt) {
+        for (int q = tid; q < FA * K; q += nt) {          // pass along x from the coefficients
             const int ar = q / K, t = q - ar * K;
-            const int base = ar * NP + (ax == 1 ? (t % P) + P * P * (t / P) : t);
+            const long long g = g0 + ar;
+            if (g >= narr) continue;
+            const int ly = t % P, lz = t / P;
+            const double *src = s + g * NM + (PN ? BS::off(ly, lz) : t * P);
+            const int nl = PN ? BS::len(ly, lz) : P;
             T x[P];
 #pragma unroll
-            for (int k = 0; k < P; ++k) x[k] = in[base + k * S];
+            for (int k = 0; k < P; ++k) x[k] = (T)(k < nl ? src[k] : 0.0);
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 T acc = T(0);
 #pragma unroll
                 for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_B>(k, i), x[k], acc);
-                o[base + i * S] = acc;
+                X[ar * NP + t * P + i] = acc;
             }
         }
         __syncthreads();
-        T *tmp = in;
-        in = o;
-        o = tmp;
-    }
-    for (int q = tid; q < FA * NP; q += nt) {
-        const long long g = g0 + q / NP;
-        if (g < narr) out[g * NP + q % NP] = in[q];
-    }
-    __syncthreads();   // X / Y are reused by the next group
+        T *in = X, *o = Y;
+#pragma unroll
+        for (int ax = 1; ax < D; ++ax) {                  // passes along y (and z)
+            const int S = ax == 1 ? P : P * P;
+            for (int q = tid; q < FA * K; q += nt) {
+                const int ar = q / K, t = q - ar * K;
+                const int base = ar * NP + (ax == 1 ? (t % P) + P * P * (t / P) : t);
+                T x[P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) x[k] = in[base + k * S];
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int k = 0; k < P; ++k) acc = fma(mat<P, T, M_B>(k, i), x[k], acc);
+                    o[base + i * S] = acc;
+                }
+            }
+            __syncthreads();
+            T *tmp = in;
+            in = o;
+            o = tmp;
+        }
+        for (int q = tid; q < FA * NP; q += nt) {
+            const long long g = g0 + q / NP;
+            if (g < narr) out[g * NP + q % NP] = in[q];
+        }
+        __syncthreads();   // X / Y are reused by the next group
     }
 }
 
 template <int D, int P, typename T, int PH>
-size_t vol_lds_bytes(int C, int Fx)
+size_t vol_lds_bytes(int C, int NU)
 {
     constexpr int NP = Pad<P>::PP * ipow(P, D - 1);   // padded per-cell array
     constexpr int F = Fld<D, PH>::F;
     return vol_hdr_bytes<D>(C) + vol_m0_bytes<D, P>(C, Fld<D, PH>::Fc) +
-           sizeof(T) * ((size_t)C * Fx * NP + (size_t)C * D * F * NP);
+           sizeof(T) * ((size_t)C * NU * NP + (size_t)C * D * F * NP);
 }
 
 // ---------------------------------------------------------------------------

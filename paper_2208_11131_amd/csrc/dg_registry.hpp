@@ -18,7 +18,7 @@ struct KernelSet {
     const void *vol_b;     // grouped (batched ensemble) variants
     const void *face_b;
     const void *cfl_b;     // FP64 units only
-    size_t (*vol_lds)(int C, int Fx);
+    size_t (*vol_lds)(int C, int NU);   // NU: point-value arrays per cell (the stored fields)
     size_t (*face_lds)(int C);
     size_t (*cfl_lds)(int C, int nt);
     const void *limit;     // positivity limiter (FP64 units only)
