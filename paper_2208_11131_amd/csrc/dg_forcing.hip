@@ -122,17 +122,21 @@ __device__ __forceinline__ void project_item(const double *__restrict__ tab, int
                                              long long item, double *__restrict__ s);
 
 // Grid-stride over the (cell, mode) items, so that any mesh fits a grid of
-// at most 2^20 blocks.
+// at most 2^20 blocks.  The table (tab_len doubles) is staged in LDS first:
+// every item reads all of it.
 template <int D>
-__global__ void __launch_bounds__(256) forcing_project_kernel(const double *__restrict__ tab, int nm, int kmax,
-                                                              int P, int NP, int basis, int n0, int n1, double lo0,
-                                                              double lo1, double lo2, double h, long long ncells,
-                                                              double *__restrict__ s)
+__global__ void __launch_bounds__(256) forcing_project_kernel(const double *__restrict__ tab, int tab_len, int nm,
+                                                              int kmax, int P, int NP, int basis, int n0, int n1,
+                                                              double lo0, double lo1, double lo2, double h,
+                                                              long long ncells, double *__restrict__ s)
 {
+    extern __shared__ double tl[];
+    for (int i = threadIdx.x; i < tab_len; i += blockDim.x) tl[i] = tab[i];
+    __syncthreads();
     const long long total = ncells * NP;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x; item < total; item += stride)
-        project_item<D>(tab, nm, kmax, P, NP, basis, n0, n1, lo0, lo1, lo2, h, item, s);
+        project_item<D>(tl, nm, kmax, P, NP, basis, n0, n1, lo0, lo1, lo2, h, item, s);
 }
 
 template <int D>
@@ -350,11 +354,12 @@ dg_status dg_forcing_project(dg_forcing *f, double *s, void *stream)
     const dim3 grid((unsigned)(blocks < (1LL << 20) ? blocks : (1LL << 20))), block(256);
     const void *fn = f->dim == 2 ? (const void *)&forcing_project_kernel<2> : (const void *)&forcing_project_kernel<3>;
     const double *t = f->d_tab;
+    int tl = (int)f->tab_len;
     int nm = f->nm, kmax = f->kmax, P = f->P, NP = f->NP, basis = f->basis, n0 = f->n[0], n1 = f->n[1];
     double lo0 = f->lo[0], lo1 = f->lo[1], lo2 = f->lo[2], h = f->h;
     long long nc = f->ncells;
-    void *args[] = {&t, &nm, &kmax, &P, &NP, &basis, &n0, &n1, &lo0, &lo1, &lo2, &h, &nc, &s};
-    if (hipLaunchKernel(fn, grid, block, args, 0, st) != hipSuccess) return DG_EDEVICE;
+    void *args[] = {&t, &tl, &nm, &kmax, &P, &NP, &basis, &n0, &n1, &lo0, &lo1, &lo2, &h, &nc, &s};
+    if (hipLaunchKernel(fn, grid, block, args, sizeof(double) * f->tab_len, st) != hipSuccess) return DG_EDEVICE;
     return DG_OK;
 }
 
