@@ -324,6 +324,14 @@ void dg_batch_free(dg_batch *b);
  * kernels without a graph. */
 dg_status dg_batch_step(dg_batch *b, double *const *w, int use_graph, void *stream);
 
+/* The same step with caller-given step sizes: box i advances by dt_dev[i]
+ * (device array of nbox doubles, 8-byte aligned, read on the device when the
+ * step runs, so a captured graph replays with whatever values the array
+ * holds then) instead of its CFL step.  A different dt_dev pointer, or
+ * alternating with dg_batch_step, captures the graph again.  dg_batch_dt
+ * then reports these values. */
+dg_status dg_batch_step_dt(dg_batch *b, double *const *w, const double *dt_dev, int use_graph, void *stream);
+
 /* Per-box step sizes of the last batched step (host array of nbox doubles).
  * Synchronises `stream`. */
 dg_status dg_batch_dt(dg_batch *b, double *dt_out, void *stream);

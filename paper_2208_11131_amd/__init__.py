@@ -81,6 +81,7 @@ _SIGS = {
                                      ctypes.POINTER(dg_av_params), ctypes.POINTER(dg_options), ctypes.POINTER(_V)]),
     "dg_batch_free": (None, [_V]),
     "dg_batch_step": (ctypes.c_int, [_V, ctypes.POINTER(_V), ctypes.c_int, _V]),
+    "dg_batch_step_dt": (ctypes.c_int, [_V, ctypes.POINTER(_V), _V, ctypes.c_int, _V]),
     "dg_batch_dt": (ctypes.c_int, [_V, _D, _V]),
     "dg_batch_box": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(_V)]),
     "dg_batch_size": (ctypes.c_int, [_V]),
@@ -312,6 +313,16 @@ def dg_batch_step(b, ws, use_graph=True, stream=None):
     _chk(lib().dg_batch_step(b, ptrs, 1 if use_graph else 0, _stream(stream)), "dg_batch_step")
 
 
+def dg_batch_step_dt(b, ws, dt, use_graph=True, stream=None):
+    """dt: float64 CUDA tensor of nbox step sizes (read when the step runs)."""
+    nbox = dg_batch_size(b)
+    if len(ws) != nbox:
+        raise ValueError("dg_batch_step_dt: %d state tensors for %d boxes" % (len(ws), nbox))
+    ptrs = (_V * nbox)(*[_dptr(w, dg_state_len(dg_batch_box(b, i))) for i, w in enumerate(ws)])
+    _chk(lib().dg_batch_step_dt(b, ptrs, _dptr(dt, nbox), 1 if use_graph else 0, _stream(stream)),
+         "dg_batch_step_dt")
+
+
 def dg_batch_dt(b, nbox, stream=None):
     out = (ctypes.c_double * nbox)()
     _chk(lib().dg_batch_dt(b, out, _stream(stream)), "dg_batch_dt")
@@ -350,6 +361,10 @@ class Batch:
 
     def step(self, ws, use_graph=True, stream=None):
         dg_batch_step(self.b, ws, use_graph, stream)
+
+    def step_dt(self, ws, dt, use_graph=True, stream=None):
+        """One step of every box by the caller's step sizes dt (device tensor)."""
+        dg_batch_step_dt(self.b, ws, dt, use_graph, stream)
 
     def dts(self, stream=None):
         return dg_batch_dt(self.b, self.nbox, stream)

@@ -112,7 +112,8 @@ struct BoxDesc {
     int *flag;
     long long start[3];
     long long nblocks[3];
-    int cells_per_block, faces_per_block, cfl_cells, pad;
+    int cells_per_block, faces_per_block, cfl_cells;
+    int bidx;            // index of the box in its batch
 };
 
 // RK stage of a grouped launch: register roles (-1 = none) and Shu-Osher

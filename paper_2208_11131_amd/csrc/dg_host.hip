@@ -296,6 +296,20 @@ __global__ void __launch_bounds__(kFinT) cfl_finalize_batched(const dgk::BoxDesc
     }
 }
 
+// Caller-given step sizes of a batched step (dg_batch_step_dt): box i of a
+// grouped launch takes dt_in[bidx] as its dt (read when the step runs).
+__global__ void __launch_bounds__(64) dt_in_batched(const dgk::BoxDesc *boxes, int n, const double *dt_in)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) boxes[i].dt[0] = dt_in[boxes[i].bidx];
+}
+
+// The same for one box: dst[0] = src[0].
+__global__ void __launch_bounds__(64) dt_in_single(const double *src, double *dst)
+{
+    if (threadIdx.x == 0) dst[0] = src[0];
+}
+
 // Neumaier-compensated add of x into (s, c).
 __device__ __forceinline__ void nadd(double &s, double &c, double x)
 {
@@ -1306,6 +1320,8 @@ struct dg_batch {
     std::vector<Group> groups;
     std::vector<int> large;        // boxes stepped by their own kernels inside the step
     std::vector<double *> wptr;
+    const double *dt_in = nullptr; // caller's per-box step sizes (device) of the step being enqueued, or null (CFL)
+    const double *graph_dt = nullptr;   // dt_in of the captured graph
     bool have_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1395,7 +1411,15 @@ dg_status unit_enqueue(dg_batch *b, int u, hipStream_t s)
     if (u < (int)b->large.size()) {
         const int i = b->large[u];
         dg_ctx *c = b->box[i];
-        dg_status st = run_cfl(c, b->wptr[i], nullptr, s, false);
+        dg_status st = DG_OK;
+        if (b->dt_in) {
+            const double *src = b->dt_in + i;
+            double *dst = c->scal;
+            void *args[] = {&src, &dst};
+            if (!ok(hipLaunchKernel((const void *)&dt_in_single, dim3(1), dim3(64), args, 0, s))) return DG_EDEVICE;
+        } else {
+            st = run_cfl(c, b->wptr[i], nullptr, s, false);
+        }
         if (st == DG_OK) st = rk_step(c, b->wptr[i], 0.0, c->scal, s);
         c->fin_pending = false;
         return st;
@@ -1404,12 +1428,18 @@ dg_status unit_enqueue(dg_batch *b, int u, hipStream_t s)
         Group &g = b->groups[u - b->large.size()];
         const int n = (int)g.boxes.size();
         dgk::BoxDesc *d = g.d_desc;
-        {
-            void *args[] = {&d, (void *)&n};
-            if (!ok(hipLaunchKernel(g.ks64.cfl_b, dim3((unsigned)g.nblk[2]), dim3(g.cfl_T), args, g.cfl_lds, s)))
+        if (b->dt_in) {
+            const double *src = b->dt_in;
+            void *args[] = {&d, (void *)&n, &src};
+            if (!ok(hipLaunchKernel((const void *)&dt_in_batched, dim3((unsigned)((n + 63) / 64)), dim3(64), args, 0,
+                                    s)))
                 return DG_EDEVICE;
-        }
-        {
+        } else {
+            {
+                void *args[] = {&d, (void *)&n};
+                if (!ok(hipLaunchKernel(g.ks64.cfl_b, dim3((unsigned)g.nblk[2]), dim3(g.cfl_T), args, g.cfl_lds, s)))
+                    return DG_EDEVICE;
+            }
             double cfl = b->cfl;
             void *args[] = {&d, &cfl};
             if (!ok(hipLaunchKernel((const void *)&cfl_finalize_batched, dim3(n), dim3(kFinT), args, 0, s)))
@@ -1544,6 +1574,7 @@ static dg_status batch_init_impl(int nbox, const dg_mesh *meshes, const int *ord
             d.cells_per_block = c->vol_C;
             d.faces_per_block = c->face_C;
             d.cfl_cells = c->cfl_C;
+            d.bidx = i;
             d.nblocks[0] = (c->ncells + c->vol_C - 1) / c->vol_C;
             long long nf = 0;
             for (int a = 0; a < c->dim; ++a) {
@@ -1609,13 +1640,17 @@ void dg_batch_free(dg_batch *b)
     delete b;
 }
 
-dg_status dg_batch_step(dg_batch *b, double *const *w, int use_graph, void *stream)
+namespace {
+
+// dg_batch_step (dt_dev = null: per-box CFL steps) and dg_batch_step_dt.
+dg_status batch_step(dg_batch *b, double *const *w, const double *dt_dev, int use_graph, void *stream)
 {
-    if (!b || !w) return DG_EINVAL;
+    if (!b || !w || ((uintptr_t)dt_dev & 7)) return DG_EINVAL;
     for (int i = 0; i < b->nbox; ++i)
         if (!w[i] || !aligned16(w[i])) return DG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    bool changed = false;
+    b->dt_in = dt_dev;
+    bool changed = b->have_graph && b->graph_dt != dt_dev;   // another step-size source: capture again
     for (int i = 0; i < b->nbox; ++i)
         if (b->wptr[i] != w[i]) changed = true;
     if (changed) {
@@ -1655,8 +1690,22 @@ dg_status dg_batch_step(dg_batch *b, double *const *w, int use_graph, void *stre
         b->graph = g;
         b->exec = ex;
         b->have_graph = true;
+        b->graph_dt = dt_dev;
     }
     return ok(hipGraphLaunch(b->exec, s)) ? DG_OK : DG_EDEVICE;
+}
+
+}  // namespace
+
+dg_status dg_batch_step(dg_batch *b, double *const *w, int use_graph, void *stream)
+{
+    return batch_step(b, w, nullptr, use_graph, stream);
+}
+
+dg_status dg_batch_step_dt(dg_batch *b, double *const *w, const double *dt_dev, int use_graph, void *stream)
+{
+    if (!dt_dev) return DG_EINVAL;
+    return batch_step(b, w, dt_dev, use_graph, stream);
 }
 
 dg_status dg_batch_dt(dg_batch *b, double *dt_out, void *stream)

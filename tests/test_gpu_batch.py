@@ -155,3 +155,36 @@ def test_binding_rejects_wrong_lengths_before_launch():
     with pytest.raises(ValueError):
         dg.dg_get_sensor_rate(s2.ctx, torch.zeros(21, dtype=torch.float64, device="cuda"))
     assert dg.dg_shape(s2.ctx) == (2, 3, 20, 5)
+
+
+def test_batch_step_with_given_dt():
+    """dg_batch_step_dt: every box advances by the caller's dt_dev[i] (read on
+    the device when the step runs).  Equal bitwise to per-box dg_step with the
+    same dt, for grouped and large (own-kernel) boxes; a replay of the captured
+    graph picks up new values written into dt_dev; a CFL step afterwards
+    (dg_batch_step) captures again and still equals per-box stepping."""
+    sides = [8, 12, 256, 8]
+    orders = [2, 4, 3, 3]
+    say("batch with given dt", sides, orders)
+    bt = dg.Batch(2, sides, orders, 5.0 / 3.0, cfl=0.5)
+    w0 = [W.ensemble_box(b, sides[b], orders[b]).numpy() for b in range(len(sides))]
+    wb = [torch.tensor(x, device="cuda") for x in w0]
+    wp = [torch.tensor(x, device="cuda") for x in w0]
+    dt = torch.tensor([1e-3, 7e-4, 2e-4, 5e-4], dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        if rep == 2:
+            dt.mul_(0.5)                                      # new values, same array: graph replay
+        bt.step_dt(wb, dt, use_graph=True)
+        for i in range(len(sides)):
+            dg.dg_step(dg.dg_batch_box(bt.b, i), wp[i], float(dt[i]))
+        torch.cuda.synchronize()
+        for i in range(len(sides)):
+            assert torch.equal(wb[i], wp[i]), (rep, i)
+    assert bt.dts() == dt.cpu().tolist()
+    bt.step(wb, use_graph=True)                               # back to CFL steps
+    for i in range(len(sides)):
+        bt.box_step_cfl(i, wp[i])
+        assert torch.equal(wb[i], wp[i]), i
+        assert bt.box_check(i) == 0
+    with pytest.raises(ValueError):
+        bt.step_dt(wb, dt[:3])
