@@ -96,9 +96,10 @@ typedef enum { DG_PREC_FP64 = 0, DG_PREC_FP32_BULK = 1 } dg_precision;
 /* Options (NULL = defaults): precision FP64; basis 0 = tensor set Q_n
  * (p^dim modes per field), 1 = total-degree set P_n of Sec. 2.3 (the modes
  * of degree l_x + l_y [+ l_z] <= n: (n+1)(n+2)/2 in 2D, (n+1)(n+2)(n+3)/6 in
- * 3D, stored in the order l_z, l_y, l_x ascending with l_x fastest; Euler and
- * Navier-Stokes only; the interface recovery then uses the basis of total
- * degree <= n+1 and the sensor's top modes are those of total degree n); cfl =
+ * 3D, stored in the order l_z, l_y, l_x ascending with l_x fastest; every
+ * physics of the tensor basis; the interface recovery then uses the basis of
+ * total degree <= n+1 and the sensor's top modes are those of total degree
+ * n; not for batched ensembles); cfl =
  * f_CFL of eq. timestep (default 0.5);
  * launch tiles (0 = built-in tuned table): cells per volume block, faces per
  * face-kernel pencil, threads per volume / face block (multiples of 64,

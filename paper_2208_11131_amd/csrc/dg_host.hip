@@ -392,7 +392,7 @@ struct dg_ctx {
     int device;
     bool grad;
     int phys;    // 0 Euler, 1 Navier-Stokes, 2 artificial viscosity, 3 Navier-Stokes + tracer,
-                 // 4 / 5 Euler / Navier-Stokes on the total-degree basis
+                 // 4..7 the same four on the total-degree basis
     KernelSet ks, ks64;
     const void *vol_fixed[2];   // fixed-tile volume kernels (no forcing / forcing) for the tile in use, or null
     const void *face_fixed;     // fixed-tile face kernel for the tile in use, or null
@@ -814,7 +814,6 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     }
     const bool av_on = av && av->enabled;
     if (av_on && o.tracer) return DG_EUNSUPPORTED;   // no AV variant carries the tracer
-    if (o.basis == 1 && (av_on || o.tracer)) return DG_EUNSUPPORTED;   // P_n: Euler and Navier-Stokes
     if (av_on && (!(av->f_tau > 0.0) || !(av->alpha_max >= 0.0) || !(av->scale >= 0.0) || !(av->f_v >= 0.0) ||
                   !(av->f_w >= 0.0) || !(av->s_onset >= 0.0)))
         return DG_EINVAL;
@@ -889,7 +888,7 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
     }
     c->grad = ph.ns_on || ph.av_on;
     c->phys = ph.av_on ? 2 : (o.tracer ? 3 : (ph.ns_on ? 1 : 0));
-    if (o.basis == 1) c->phys = ph.ns_on ? 5 : 4;
+    if (o.basis == 1) c->phys += 4;   // the same physics on the total-degree basis
     get_kernels(d, c->precision, order, c->phys, &c->ks);
     get_kernels(d, DG_PREC_FP64, order, c->phys, &c->ks64);
     if (!c->ks.vol || !c->ks.face || !c->ks64.cfl) {

@@ -1,6 +1,6 @@
 // Kernel instantiations: dim = 2, bulk precision float, orders 1..8,
 // physics variants Euler / Navier-Stokes / artificial viscosity /
-// Navier-Stokes with the passive tracer, and Euler / Navier-Stokes on the
+// Navier-Stokes with the passive tracer, and the same four on the
 // total-degree basis.
 #include "dg_kernels.hpp"
 #include "dg_registry.hpp"
@@ -38,8 +38,12 @@ void pick(int ph, KernelSet *k)
         fill<P, 3>(k);
     else if (ph == 4)
         fill<P, 4>(k);
-    else
+    else if (ph == 5)
         fill<P, 5>(k);
+    else if (ph == 6)
+        fill<P, 6>(k);
+    else
+        fill<P, 7>(k);
 }
 }  // namespace
 

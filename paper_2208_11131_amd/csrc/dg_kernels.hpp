@@ -248,9 +248,9 @@ __device__ __forceinline__ void dt_lift_pass(const T *__restrict__ in, T *__rest
 
 // Fields per physics variant: PH = 0 Euler, 1 Navier-Stokes, 2 artificial
 // viscosity (alpha field; Navier-Stokes terms switched at run time),
-// 3 Navier-Stokes with the passive tracer c rho (Sec. 3.4); PH = 4 / 5 are
-// Euler / Navier-Stokes on the total-degree basis P_n (Sec. 2.3).  Fc
-// conserved fields carry face fluxes: the D + 2 hydro fields and the tracer.
+// 3 Navier-Stokes with the passive tracer c rho (Sec. 3.4); PH = 4..7 are
+// the same four on the total-degree basis P_n (Sec. 2.3).  Fc conserved
+// fields carry face fluxes: the D + 2 hydro fields and the tracer.
 template <int D, int PH>
 struct Fld {
     static constexpr bool PN = PH >= 4;
@@ -1492,17 +1492,18 @@ __device__ __forceinline__ void vol_body(const Phys &ph, const Geo &geo, const V
         if constexpr (Fld<D, PH>::AV) if (a.R_out) {
             const double *wr = a.cur + cc * FNP;
             double Aa = 0.0, Tt = 0.0, ad = 0.0, td = 0.0;
+            // density modes in tensor order j (P_n: those of the basis, read
+            // from their storage index); Vl holds the modal RHS in the padded
+            // tensor layout
             for (int m = 0; m < NP; ++m) {
-                const double x = wr[m];
+                const int l0 = m % P, l1 = (m / P) % P, l2 = (D == 3) ? m / (P * P) : 0;
+                const int id = BS::idx(l0, l1, l2);
+                if (id < 0) continue;
+                const double x = wr[id];
                 const double xd = pref * (double)Vl[cl * NAP + ppos<P>(m)];
                 Aa += x * x;
                 ad += x * xd;
-                bool tp = false;
-                int r = m;
-                for (int b = 0; b < D; ++b) {
-                    tp = tp || (r % P == P - 1);
-                    r /= P;
-                }
+                const bool tp = PN ? (l0 + l1 + l2 == P - 1) : (l0 == P - 1 || l1 == P - 1 || (D == 3 && l2 == P - 1));
                 if (tp) {
                     Tt += x * x;
                     td += x * xd;
@@ -2070,7 +2071,7 @@ template <int DIM, int PREC, typename T, size_t I, int FO>
 FixedVol fixed_vol_entry()
 {
     constexpr TileEntry e = kTiles[I];
-    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 5 &&
+    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 7 &&
                   e.vol_C > 0 && e.vol_T >= 64 && e.vol_T <= 512 && e.vol_T % 64 == 0 && (FO == 0 || DIM == 3))
         return FixedVol{e.order, e.phys, e.vol_C, e.vol_T, FO,
                         (const void *)&vol_kernel_fixed<DIM, e.order, T, e.phys, e.vol_C, e.vol_T, FO>,
@@ -2085,7 +2086,7 @@ template <int DIM, int PREC, typename T, size_t I>
 FixedVol fixed_face_entry()
 {
     constexpr TileEntry e = kTiles[I];
-    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 5 &&
+    if constexpr (e.dim == DIM && e.prec == PREC && e.order >= 1 && e.order <= MAXP && e.phys >= 0 && e.phys <= 7 &&
                   e.face_C > 0 && e.face_T >= 64 && e.face_T <= 512 && e.face_T % 64 == 0)
         return FixedVol{e.order, e.phys, e.face_C, e.face_T, 0,
                         (const void *)&face_kernel_fixed<DIM, e.order, T, e.phys, e.face_C, e.face_T>,

@@ -8,8 +8,8 @@ namespace dgk {
 
 // Kernels and LDS-size functions of one (dim, order, precision, physics)
 // instantiation; physics PH = 0 Euler, 1 Navier-Stokes, 2 artificial
-// viscosity, 3 Navier-Stokes with the tracer, 4 / 5 Euler / Navier-Stokes on
-// the total-degree basis.  The function pointers are the host stubs of
+// viscosity, 3 Navier-Stokes with the tracer, 4..7 the same on the
+// total-degree basis.  The function pointers are the host stubs of
 // __global__ functions, launched with hipLaunchKernel.
 struct KernelSet {
     const void *vol;

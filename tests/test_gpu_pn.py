@@ -141,3 +141,85 @@ def test_pn_driving_projection():
     e = np.abs(s - ref).max() / np.abs(ref).max()
     say("  P_n projection err %.2e" % e)
     assert e <= 1e-13
+
+
+def restrict_pn(q, dim, order):
+    """Tensor-basis coefficients [cell][field][p^d] -> the P_n modes in their storage order."""
+    degq = O.mode_degrees(order, dim, 0)
+    degp = O.mode_degrees(order, dim, 1)
+    idx = [int(np.nonzero((degq == d).all(axis=1))[0][0]) for d in degp]
+    return np.ascontiguousarray(q[:, :, idx])
+
+
+@pytest.mark.parametrize("dim,n,order,bc", [(2, (11, 7), 3, None), (2, (9, 8), 6, (2, 0)), (3, (4, 3, 3), 4, None)])
+def test_pn_av_rhs_and_steps(dim, n, order, bc):
+    """Artificial viscosity on P_n (Sec. 4.1 with the basis of Sec. 2.3; top
+    modes = total degree n): the RHS with a nonzero previous sensor rate (the
+    wiggle source) within 1e-12 of the oracle's rounding scale; three SSP-RK
+    steps, whose stage 1 stores d ln S/dt, within 1e-12 per field group and
+    the stored rates within 1e-10 of their maximum."""
+    say("P_n AV", dim, n, order, bc)
+    h = 1.0 / n[0]
+    av = {"f_v": 2.5, "f_w": 0.2}
+    ref = O.Problem(dim, n, h, order, 1.4, nu=3e-3, kappa=3e-3, bc=bc, av=av, basis=1)
+    gpu = dg.Solver(dim, n, order, 1.4, nu=3e-3, kappa=3e-3, hi=[n[a] * h for a in range(dim)], bc=bc, av=av,
+                    basis=1)
+    q = W.random_smooth(dim, n, order, nfields=ref.nfields, seed=order + 50, amp=0.08, alpha_level=0.3,
+                        vbase=(0.2, -0.1, 0.1)).numpy()
+    w0 = restrict_pn(q, dim, order)
+    R = np.linspace(-1.0, 2.0, ref.ncells)
+    gpu.set_sensor_rate(torch.tensor(R, device="cuda"))
+    L = gpu.rhs(torch.tensor(w0, device="cuda")).cpu().numpy()
+    e = rhs_err(L, ref.rhs(w0, R_prev=R), ref.rhs_abs(w0, R_prev=R), dim)
+    say("  rhs err / rounding scale %.2e" % e)
+    assert e <= 1e-12
+    gpu.set_sensor_rate(torch.zeros(ref.ncells, dtype=torch.float64, device="cuda"))
+    w = torch.tensor(w0, device="cuda")
+    wr, Rr = w0, np.zeros(ref.ncells)
+    dt = 0.5 * ref.max_dt(w0)[0]
+    for _ in range(3):
+        gpu.step(w, dt)
+        wr, Rr = ref.step(wr, dt, Rr)
+    assert gpu.check() == 0
+    es = state_err(w.cpu().numpy(), wr, dim, mom_scale=momentum_scale(ref, wr))
+    Rg = gpu.get_sensor_rate().cpu().numpy()
+    eR = np.abs(Rg - Rr).max() / max(np.abs(Rr).max(), 1e-300)
+    say("  state err %.2e, sensor-rate err %.2e (max |R| %.2e)" % (es, eR, np.abs(Rr).max()))
+    assert es <= 1e-12
+    assert eR <= 1e-10
+
+
+@pytest.mark.parametrize("dim,n,order", [(2, (11, 7), 4), (3, (4, 3, 3), 3)])
+def test_pn_tracer_rhs_and_steps(dim, n, order):
+    """The passive tracer on P_n (Sec. 3.4 with the basis of Sec. 2.3): RHS
+    within 1e-12 of the oracle's rounding scale, five steps within 1e-12 per
+    field group, the tracer total conserved to FP64 rounding."""
+    say("P_n tracer", dim, n, order)
+    h = 1.0 / n[0]
+    ref = O.Problem(dim, n, h, order, 1.4, nu=3e-3, kappa=3e-3, tracer=True, eta=5e-3, basis=1)
+    gpu = dg.Solver(dim, n, order, 1.4, nu=3e-3, kappa=3e-3, hi=[n[a] * h for a in range(dim)], tracer=True,
+                    eta=5e-3, basis=1)
+    hyd = W.random_smooth(dim, n, order, seed=order + 60, amp=0.08, vbase=(0.2, -0.1, 0.1)).numpy()
+    rng = np.random.default_rng(order + 61)
+    c = 0.05 * rng.standard_normal(hyd[:, :1, :].shape) * 0.5 ** np.arange(order ** dim)
+    c[:, 0, 0] = 0.5 + 0.2 * rng.random(hyd.shape[0])
+    q = np.concatenate([hyd, c * hyd[:, :1, :1]], axis=1)
+    w0 = restrict_pn(q, dim, order)
+    L = gpu.rhs(torch.tensor(w0, device="cuda")).cpu().numpy()
+    e = rhs_err(L, ref.rhs(w0), ref.rhs_abs(w0), dim)
+    say("  rhs err / rounding scale %.2e" % e)
+    assert e <= 1e-12
+    w = torch.tensor(w0, device="cuda")
+    t0 = np.array(gpu.totals(w))
+    wr = w0
+    dt = 0.5 * ref.max_dt(w0)[0]
+    for _ in range(5):
+        gpu.step(w, dt)
+        wr, _ = ref.step(wr, dt)
+    assert gpu.check() == 0
+    es = state_err(w.cpu().numpy(), wr, dim, mom_scale=momentum_scale(ref, wr))
+    t1 = np.array(gpu.totals(w))
+    drift = abs(t1[-1] - t0[-1]) / abs(t0[-1])
+    say("  state err %.2e, tracer-total drift %.1e" % (es, drift))
+    assert es <= 1e-12
+    assert drift <= 1e-13
