@@ -223,3 +223,28 @@ def test_pn_tracer_rhs_and_steps(dim, n, order):
     say("  state err %.2e, tracer-total drift %.1e" % (es, drift))
     assert es <= 1e-12
     assert drift <= 1e-13
+
+
+def test_pn_limiter_with_av():
+    """The positivity limiter on P_n with the AV field (it scales the higher
+    weights of every field, alpha included): the same cells change and the
+    limited states agree with the oracle to 1e-12."""
+    dim, n, order = 2, (9, 7), 4
+    h = 1.0 / n[0]
+    ref = O.Problem(dim, n, h, order, 1.4, av={}, basis=1)
+    gpu = dg.Solver(dim, n, order, 1.4, hi=[n[a] * h for a in range(dim)], av={}, basis=1)
+    q = W.random_smooth(dim, n, order, nfields=ref.nfields, seed=77, amp=0.08, alpha_level=0.3,
+                        vbase=(0.2, -0.1, 0.1)).numpy()
+    w0 = restrict_pn(q, dim, order)
+    rng = np.random.default_rng(4)
+    sel = rng.random(w0.shape[0]) < 0.4
+    w0[sel, 0, 1:] += 0.6 * rng.standard_normal((int(sel.sum()), w0.shape[2] - 1))
+    wr, nchg = ref.limit(w0)
+    assert nchg >= 3
+    w = torch.tensor(w0, device="cuda")
+    gpu.limit(w)
+    wg = w.cpu().numpy()
+    np.testing.assert_array_equal(np.any(wg != w0, axis=(1, 2)), np.any(wr != w0, axis=(1, 2)))
+    e = state_err(wg, wr, dim, mom_scale=momentum_scale(ref, wr))
+    say("  P_n AV limiter state err %.2e (%d cells changed)" % (e, nchg))
+    assert e <= 1e-12
