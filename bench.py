@@ -155,14 +155,20 @@ def make_workload(name, order, device, precision):
         s.set_forcing(f)
         dt0 = s.max_dt(w)[0]
         every = max(1, int(math.ceil(0.01 / dt0)))            # OU update interval 0.01
-        state = {"k": 1}
+        state = {"k": 1, "step": 0}
 
-        def refresh(step):
+        def refresh():
+            # called before every step of the run (warm-up and timed steps
+            # alike): the OU update and projection every `every` steps
+            step = state["step"]
+            state["step"] += 1
             if step % every == 0:
                 drv.update(noise[state["k"] % len(noise)], every * dt0)
                 state["k"] += 1
                 drv.project(f)
                 s.set_forcing(f)                           # the library re-evaluates it at the Gauss points
+                return True
+            return False
         desc = {"workload": "driven_turbulence_3d" + ("_pn" if basis else ""), "cells": [n, n, n], "order": order,
                 "fields": 5, "basis": "P_n (total degree)" if basis else "Q_n (tensor)",
                 "modes": s.nmodes, "physics": "navier_stokes nu=kappa=2e-5 + OU driving", "gamma": 1.0001,
@@ -199,7 +205,7 @@ def measure(name, order, precision, steps, warmup, repeats=1, device="cuda"):
     for i in range(warmup):
         dg.dg_timing_enable(s.ctx, i >= warmup - len(sampled))
         if refresh:
-            refresh(i)
+            refresh()
         s.step_cfl(w)
     dg.dg_timing_enable(s.ctx, False)
     torch.cuda.synchronize()
@@ -212,6 +218,7 @@ def measure(name, order, precision, steps, warmup, repeats=1, device="cuda"):
     stream = torch.cuda.current_stream()
     runs = []
     wall = 0.0
+    updates = 0
     for _ in range(repeats):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -220,15 +227,18 @@ def measure(name, order, precision, steps, warmup, repeats=1, device="cuda"):
         e0.record(stream)
         for i in range(steps):
             dg.dg_timing_enable(s.ctx, i in sampled)
-            if refresh:
-                refresh(warmup + i)
+            if refresh and refresh():
+                updates += 1
             s.step_cfl(w)
         dg.dg_timing_enable(s.ctx, False)
         e1.record(stream)
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
         runs.append(e0.elapsed_time(e1))
-    ms = float(np.median(runs))
+    # with periodic driving updates only some repeats hold one: the mean over
+    # the repeats (the whole timed region) carries their cost at its rate
+    ms = float(np.mean(runs)) if refresh else float(np.median(runs))
+    timing = "%s of %d repeats of %d steps" % ("mean" if refresh else "median", repeats, steps)
     kt = dg.dg_timing_read(s.ctx)
     err = s.check()
     if err != 0:
@@ -273,10 +283,54 @@ def measure(name, order, precision, steps, warmup, repeats=1, device="cuda"):
              "frac_alu": (vol_fl + face_fl) / st_s / 1e12 / peak_tf,
              "bytes_per_dof_by_stage": bpd}
     res = {"value": value, "stage": stage, "ms": ms, "runs_ms": runs, "wall_s": wall, "stages": stages,
-           "dofs": dofs, "desc": desc, "steps": steps, "warmup": warmup, "repeats": repeats,
+           "dofs": dofs, "desc": desc, "steps": steps, "warmup": warmup, "repeats": repeats, "timing": timing,
+           "driving_updates_timed": updates,
            "kernels": kern, "dominant": dom, "cfl_ms": kt["cfl"][0], "solver": s, "state": w,
            "forcing": f, "phys": phys}
     return res
+
+
+def measure_graph(r, steps, repeats):
+    """The measured workload's step (device CFL + SSP-RK step) captured once
+    into a HIP graph and replayed, continuing from the state of `r`.  A step
+    right after a driving-field update runs eagerly instead: that call also
+    evaluates the new field at the Gauss points, which a replay does not."""
+    s, w, phys = r["solver"], r["state"], r["phys"]
+    if phys["av"]:
+        return None                      # the sensor-rate buffers alternate per step
+    refresh = phys.get("refresh")
+    dg.dg_timing_enable(s.ctx, False)
+    s.step_cfl(w)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        s.step_cfl(w)
+    stream = torch.cuda.current_stream()
+    runs, eager = [], 0
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(steps):
+            if refresh and refresh():
+                s.step_cfl(w)
+                eager += 1
+            else:
+                g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1))
+    err = s.check()
+    if err != 0:
+        raise RuntimeError("the graph replays produced a non-physical or non-finite state: %s" % dg.status_str(err))
+    ms = float(np.mean(runs)) if refresh else float(np.median(runs))
+    del g
+    return {"value": r["dofs"] * r["stages"] * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+            "eager_ms_per_step": r["ms"] / r["steps"], "speedup_vs_eager": r["ms"] / r["steps"] / (ms / steps),
+            "repeats_ms": runs, "eager_steps_after_driving_updates": eager,
+            "timing": "%s of %d repeats of %d steps, one captured step per replay" %
+                      ("mean" if refresh else "median", repeats, steps)}
 
 
 def kernel_record(r):
@@ -472,7 +526,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32-bulk/f64-state", "data": "synthetic",
         "config": dict(res["desc"], stages_per_step=res["stages"], dofs=res["dofs"],
                        step="device CFL reduction + full SSP-RK step",
-                       timing="median of %d repeats of %d steps" % (args.repeats, args.steps),
+                       timing=res["timing"], driving_updates_timed=res["driving_updates_timed"],
                        repeats_ms=res["runs_ms"]),
         "roofline": roof,
         "stage_roofline": res["stage"],
@@ -481,6 +535,9 @@ def main():
     w64 = res["state"].cpu().numpy()
     dim = res["phys"]["dim"]
     nsteps64 = args.warmup + args.steps * args.repeats
+    if not args.no_extras:
+        print("bench: graph replay", file=sys.stderr, flush=True)
+        line["graph_replay"] = measure_graph(res, args.steps, args.repeats)
     del res
     torch.cuda.empty_cache()
     if not args.no_extras:

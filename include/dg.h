@@ -173,7 +173,16 @@ dg_status dg_step(dg_ctx *ctx, double *w, double dt, void *stream);
 
 /* As dg_step, with dt = f_CFL h / (2 p (c_max + v_max)) computed on the
  * device from w (eq. timestep) and never copied to the host; if dt_dev is
- * not NULL the step size (double) is also stored there (device pointer). */
+ * not NULL the step size (double) is also stored there (device pointer).
+ *
+ * HIP graphs: dg_rhs, dg_step, dg_step_cfl and dg_limit enqueue kernel
+ * launches only (no allocation, copy, memset or synchronisation), so they
+ * may be captured from `stream`.  A replay repeats the captured launches
+ * with the captured pointers and scalars (dg_step's dt included).  With
+ * artificial viscosity the context alternates two sensor-rate buffers from
+ * step to step: capture an even number of steps.  A driving field that
+ * dg_set_forcing left pending is evaluated by the next call, captured or
+ * not; replays evaluate it again only if it was captured. */
 dg_status dg_step_cfl(dg_ctx *ctx, double *w, double *dt_dev, void *stream);
 
 /* Positivity limiter (Sec. 4.2) on w (device, in place), every cell: with
