@@ -946,7 +946,9 @@ dg_status dg_init(const dg_mesh *mesh, int order, double gamma, double nu, doubl
             return DG_EUNSUPPORTED;
         }
     }
-    c->cfl_C = std::max(1, 256 / c->NP);
+    // cells per CFL tile: the HBM pass (one item per field and line of the
+    // conserved fields) fills one round of the 256 threads
+    c->cfl_C = std::max(1, 256 / ((d + 2) * (c->NP / c->P)));
     c->cfl_T = 256;
     while (c->cfl_C > 1 && c->ks64.cfl_lds(c->cfl_C, c->cfl_T) > 64 * 1024) --c->cfl_C;
     c->cfl_lds = c->ks64.cfl_lds(c->cfl_C, c->cfl_T);
